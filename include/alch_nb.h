@@ -1,0 +1,244 @@
+/*
+ * alch_nb.h - C ABI of the MI355X alchemical short-range nonbonded library.
+ *
+ * The library evaluates the lambda-dependent potential U(x, lambda) of the
+ * paper's lambda-dynamics method (Linear Basis Function section, eq. 4):
+ *   U = U_solv + U_solu + (lambda-scaled solute-solvent interactions),
+ * restricted to its short-range nonbonded part, together with the atomic
+ * forces -dU/dx and the generalized force dU/dlambda that drives lambda and
+ * whose conditional mean is integrated for the free energy (eq. 2).
+ *
+ * Pair potential (Angstrom, kcal/mol, e):
+ *   every unordered, non-excluded pair i<j with minimum-image distance
+ *   r < cutoff is evaluated once, with Lorentz-Berthelot combination.
+ *   Pairs inside the solvent or inside the solute:  LJ(r) S(r) + k_e q q D(r).
+ *   Solute-solvent pairs, ALCH_NB_BEUTLER_DSF (default):
+ *       lv 4 eps (x^2 - x) S(r) + le k_e q q D(r),
+ *       x = 1/(sc_alpha (1 - lv) + (r/sigma)^6), lv = min(1, 2 lambda),
+ *       le = max(0, 2 lambda - 1)  (the conventional soft core the paper
+ *       contrasts with LBF; Linear Basis Function section).
+ *   Solute-solvent pairs, ALCH_NB_LBF_DSF (the paper's eq. 4-10):
+ *       hA(lambda) [LJ S + k_e q q D] + hB(lambda) eps u_cap(r/sigma) S.
+ *   S(r) = 1 - S22((r - r_s)/w) on (r_s = cutoff - w, cutoff) (eq. 9 as the
+ *   switch; Simulation Details section); D(r) is the damped shifted-force
+ *   Coulomb kernel erfc(a r)/r - erfc(a rc)/rc + [erfc(a rc)/rc^2 +
+ *   2a/sqrt(pi) exp(-a^2 rc^2)/rc](r - rc), a = dsf_alpha, k_e = 332.06371.
+ *   dU/dlambda uses the left derivative at the Beutler kink lambda = 1/2.
+ *
+ * Conventions
+ *   - All functions return alch_nb_status (0 = OK).  No exception crosses
+ *     the ABI.  alch_nb_strerror() names each code.
+ *   - "host" pointers are read during the call only; "device" pointers must
+ *     point to device memory that stays valid until the bound stream has
+ *     executed the enqueued work.  The library never allocates device
+ *     memory: alch_nb_workspace_size() reports the bytes it needs and the
+ *     caller hands a buffer of that size to alch_nb_bind().
+ *   - Work is enqueued on the stream given to alch_nb_bind() (a hipStream_t
+ *     passed as void*; NULL = the null stream) and the calls return without
+ *     waiting.  Conditions detected on the device set sticky flag bits read
+ *     with alch_nb_get_flags(), which synchronizes the stream.
+ *   - One context is used by one host thread at a time.
+ *   - Atom order: the concatenation of the systems passed to
+ *     alch_nb_create(), each in its own order.  Positions and forces are
+ *     float64 [N_total][3], row major.
+ *   - Results are bit-identical from run to run for a fixed context,
+ *     precision and variant (forces are summed in 64-bit fixed point).
+ */
+#ifndef ALCH_NB_H
+#define ALCH_NB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t alch_nb_status;
+enum {
+  ALCH_NB_OK = 0,
+  ALCH_NB_E_INVALID_ARG = 1,   /* a pointer, size, index or parameter is invalid */
+  ALCH_NB_E_BOX_TOO_SMALL = 2, /* cutoff + skin exceeds half the shortest box edge */
+  ALCH_NB_E_UNSUPPORTED = 3,   /* valid request this build does not implement */
+  ALCH_NB_E_CAPACITY = 4,      /* the neighbour list outgrew its workspace */
+  ALCH_NB_E_HIP = 5,           /* a HIP runtime call failed (see alch_nb_last_hip_error) */
+  ALCH_NB_E_NOT_BOUND = 6,     /* the context has no workspace/stream yet */
+  ALCH_NB_E_NO_DEVICE = 7      /* no usable GPU */
+};
+
+enum { ALCH_NB_BEUTLER_DSF = 0, ALCH_NB_LBF_DSF = 1 };     /* schedule */
+enum { ALCH_NB_FP32_FIXED = 0, ALCH_NB_FP64 = 1 };         /* precision */
+
+/* alch_nb_compute() flags */
+enum { ALCH_NB_AUTO_REBUILD = 1u, ALCH_NB_FORCE_REBUILD = 2u };
+
+/* sticky device flags */
+enum {
+  ALCH_NB_FLAG_FIXED_OVERFLOW = 1u, /* a force left the fixed-point range */
+  ALCH_NB_FLAG_SKIN_EXCEEDED = 2u,  /* an atom moved > skin/2 since the list was built (no auto rebuild) */
+  ALCH_NB_FLAG_NONFINITE = 4u,      /* a position was NaN or infinite */
+  ALCH_NB_FLAG_LAMBDA_RANGE = 8u,   /* a lambda outside [0,1] was clamped */
+  ALCH_NB_FLAG_CAPACITY = 16u       /* the list did not fit its capacity; results of that call are invalid */
+};
+
+/* energy-term slots of alch_nb_out.terms, per system */
+enum {
+  ALCH_NB_T_SOLV_SOLV = 0, /* solvent-solvent pair energy */
+  ALCH_NB_T_SOLU_SOLU = 1, /* solute-solute (non-excluded) pair energy */
+  ALCH_NB_T_SS_VDW = 2,    /* lambda-scaled solute-solvent van der Waals energy */
+  ALCH_NB_T_SS_ELEC = 3,   /* lambda-scaled solute-solvent electrostatic energy */
+  ALCH_NB_T_UA = 4,        /* LBF basis U_solu-solv (0 for Beutler) */
+  ALCH_NB_T_UB = 5,        /* LBF basis U_softLJ (0 for Beutler) */
+  ALCH_NB_T_DUDL_VDW = 6,  /* van der Waals part of dU/dlambda */
+  ALCH_NB_T_DUDL_ELEC = 7, /* electrostatic part of dU/dlambda */
+  ALCH_NB_T_TOTAL = 8,     /* total energy */
+  ALCH_NB_T_DUDL = 9,      /* dU/dlambda */
+  ALCH_NB_NTERMS = 10
+};
+
+typedef struct alch_nb_ctx alch_nb_ctx;
+
+/* One periodic orthorhombic box (one replica).  All pointers are host. */
+typedef struct {
+  int32_t n_atoms;            /* >= 0 */
+  const int32_t *type;        /* [n_atoms] in [0, n_types) */
+  const uint8_t *is_solute;   /* [n_atoms] 1 = alchemically coupled group, 0 = environment */
+  int32_t n_excl;             /* >= 0 */
+  const int32_t *excl;        /* [n_excl][2] local indices, i < j, sorted by (i, j), no duplicates */
+  double box[3];              /* edge lengths, Angstrom */
+} alch_nb_system;
+
+/* Parameters shared by all systems.  Pointers are host. */
+typedef struct {
+  int32_t n_types;
+  const double *sigma;        /* [n_types] > 0, Angstrom */
+  const double *epsilon;      /* [n_types] >= 0, kcal/mol */
+  const double *charge;       /* [n_types] e */
+  double cutoff;              /* r_c > 0 */
+  double skin;                /* list buffer >= 0; cutoff + skin <= min(box)/2 */
+  double switch_width;        /* LJ switch width in [0, cutoff); 0 = hard truncation */
+  double dsf_alpha;           /* DSF damping a >= 0; FP32 path needs a * cutoff <= 4 */
+  double sc_alpha;            /* Beutler soft-core alpha >= 0 (0.5) */
+  int32_t schedule;           /* ALCH_NB_BEUTLER_DSF | ALCH_NB_LBF_DSF */
+  int32_t precision;          /* ALCH_NB_FP32_FIXED | ALCH_NB_FP64 */
+  int32_t variant;            /* launch variant index, -1 = default (see alch_nb_autotune) */
+  double list_capacity_factor;/* scales the neighbour-list capacity estimate; <= 0 means 1 */
+} alch_nb_params;
+
+/* Outputs of alch_nb_compute().  Device pointers; any may be NULL. */
+typedef struct {
+  double *terms;              /* [K][ALCH_NB_NTERMS] */
+  double *forces;             /* [N_total][3]  -dU/dx, float64 for both precisions */
+  double *dudl;               /* [K] dU/dlambda */
+  int64_t *n_pairs;           /* [K] pairs with r < cutoff that were evaluated */
+} alch_nb_out;
+
+/* Gradients written by alch_nb_backward().  Device pointers; NULL skips. */
+typedef struct {
+  double *d_pos;              /* [N_total][3] accumulated: += g_k * dU_k/dx */
+  double *d_lambda;           /* [K] written: g_k * dU_k/dlambda */
+  double *d_sigma;            /* [n_types] written: sum_k g_k dU_k/dsigma_t */
+  double *d_sqrt_epsilon;     /* [n_types] written: sum_k g_k dU_k/dsqrt(eps_t) */
+  double *d_charge;           /* [n_types] written: sum_k g_k dU_k/dq_t */
+} alch_nb_grad;
+
+typedef struct {
+  int64_t n_atoms, n_systems;
+  int64_t n_superclusters, n_entries, n_units;   /* current list (valid after a sync) */
+  int64_t entry_capacity, unit_capacity;
+  int64_t n_rebuilds;                            /* list builds since bind */
+  int32_t variant;                               /* variant in use */
+  int32_t entries_per_unit, blocks;              /* launch shape of the tile kernel */
+  double tile_ms_total;                          /* summed tile-kernel time of timed calls */
+  int64_t tile_launches_timed;
+} alch_nb_stats;
+
+/* Create a context for n_systems boxes (host-only work: validation and
+ * planning; no HIP call).  *out receives the context or NULL on error. */
+alch_nb_status alch_nb_create(const alch_nb_params *params, const alch_nb_system *systems, int32_t n_systems,
+                              alch_nb_ctx **out);
+
+/* Bytes of device workspace the context needs. */
+alch_nb_status alch_nb_workspace_size(const alch_nb_ctx *ctx, size_t *bytes);
+
+/* Bind a device workspace (>= workspace_size bytes, 256-byte aligned) and a
+ * stream; uploads the static tables.  Rebinding is allowed. */
+alch_nb_status alch_nb_bind(alch_nb_ctx *ctx, void *d_workspace, size_t bytes, void *stream);
+
+/* Build the neighbour list from device positions d_pos [N_total][3]. */
+alch_nb_status alch_nb_build_list(alch_nb_ctx *ctx, const double *d_pos);
+
+/* Evaluate energies, forces and dU/dlambda at device positions d_pos
+ * [N_total][3] and device lambdas d_lambda [K].  With ALCH_NB_AUTO_REBUILD
+ * the list is rebuilt on the device when an atom moved more than skin/2
+ * since the last build (always when skin = 0); ALCH_NB_FORCE_REBUILD
+ * rebuilds unconditionally. */
+alch_nb_status alch_nb_compute(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda, uint32_t flags,
+                               const alch_nb_out *out);
+
+/* Gradients of L = sum_k g_k E_total,k for upstream device weights
+ * d_grad_energy [K], at the same positions/lambdas as the last compute. */
+alch_nb_status alch_nb_backward(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda,
+                                const double *d_grad_energy, const alch_nb_grad *grad);
+
+/* Dihedral collective variables xi_c (atom quadruples d_idx [n_cv][4],
+ * global indices) with their Cartesian gradients d_dxi [n_cv][4][3], and,
+ * when d_mass_inv [N_total] is given, the sum_i m_i^-1 |dxi/dr_i|^2 of the
+ * paper's eq. 16 into d_msum [n_cv].  With d_s and d_kappa [n_cv] the
+ * d-AFED coupling (eq. 15) energy goes to d_u_dafed [1] and its force is
+ * added to d_forces [N_total][3].  All device pointers; optional ones may be
+ * NULL. */
+alch_nb_status alch_nb_dihedrals(alch_nb_ctx *ctx, const double *d_pos, int32_t n_cv, const int32_t *d_idx,
+                                 double *d_xi, double *d_dxi, const double *d_mass_inv, double *d_msum,
+                                 const double *d_s, const double *d_kappa, double *d_u_dafed, double *d_forces);
+
+/* Lambda/OPES state update for one box (the paper's mirror-periodic theta,
+ * eq. 3, and the dual OPES bias, eqs. 11-14, on a periodic theta grid).
+ * d_state is a device array of ALCH_NB_OPES_STATE doubles laid out as
+ * described at alch_nb_opes_layout(); d_dudl [1] is dU/dlambda from the
+ * last compute.  Writes lambda to d_lambda_out [1], the bias to d_state.
+ * deposit != 0 adds a kernel at the current theta to both biases. */
+#define ALCH_NB_OPES_GRID 101
+#define ALCH_NB_OPES_STATE (16 + 4 * ALCH_NB_OPES_GRID)
+alch_nb_status alch_nb_opes_update(alch_nb_ctx *ctx, double *d_state, const double *d_dudl, double *d_lambda_out,
+                                   int32_t deposit);
+/* Offsets inside the OPES state array (host query, no HIP call). */
+alch_nb_status alch_nb_opes_layout(int32_t *offsets, int32_t n);
+
+/* Write the current list's pair set (i<j global indices, canonical FP64
+ * test r^2 < (cutoff + skin)^2 at build time) to d_pairs [cap][2] in
+ * unspecified order and its size to the host *n_out; syncs the stream.
+ * Returns ALCH_NB_E_CAPACITY if cap is too small (*n_out still set). */
+alch_nb_status alch_nb_export_pairs(alch_nb_ctx *ctx, int32_t *d_pairs, int64_t cap, int64_t *n_out);
+
+/* Record one alch_nb_compute() with AUTO_REBUILD into a HIP graph and
+ * replay it with alch_nb_launch_step().  The pointers are captured. */
+alch_nb_status alch_nb_capture_step(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda,
+                                    const alch_nb_out *out);
+alch_nb_status alch_nb_launch_step(alch_nb_ctx *ctx);
+
+/* Time every launch variant on the current list and select the fastest;
+ * results are cached in the JSON file named by $ALCHNB_TUNE_CACHE (if set). */
+alch_nb_status alch_nb_autotune(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda, int32_t reps);
+alch_nb_status alch_nb_set_variant(alch_nb_ctx *ctx, int32_t variant);
+int32_t alch_nb_num_variants(void);
+
+/* Tile-kernel timing with HIP events on the bound stream (on/off). */
+alch_nb_status alch_nb_set_timing(alch_nb_ctx *ctx, int32_t enable);
+
+/* Read and clear the sticky flags (synchronizes the stream). */
+alch_nb_status alch_nb_get_flags(alch_nb_ctx *ctx, uint32_t *flags);
+/* Statistics (synchronizes the stream). */
+alch_nb_status alch_nb_get_stats(alch_nb_ctx *ctx, alch_nb_stats *stats);
+
+void alch_nb_destroy(alch_nb_ctx *ctx);
+const char *alch_nb_strerror(alch_nb_status status);
+int32_t alch_nb_last_hip_error(const alch_nb_ctx *ctx);
+/* Algorithmic floating-point operations charged per evaluated pair, by
+ * kind: 0 = plain pair, 1 = solute-solvent pair (used for roofline reports). */
+double alch_nb_flops_per_pair(int32_t kind);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ALCH_NB_H */

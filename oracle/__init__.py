@@ -47,7 +47,7 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             P = ctypes.c_void_p
             d, i, i64 = ctypes.c_double, ctypes.c_int, ctypes.c_int64
-            lib.oracle_eval.argtypes = [i, P, P, P, i, P, P, i, P, P, P, d, d, d, d, i, d, P, P, P, P, i]
+            lib.oracle_eval.argtypes = [i, P, P, P, i, P, P, i, P, P, P, d, d, d, d, i, d, P, P, P, P, P, i]
             lib.oracle_eval.restype = i
             lib.oracle_pairs.argtypes = [i, P, i, P, P, d, P, i64, P]
             lib.oracle_pairs.restype = i
@@ -101,12 +101,14 @@ def evaluate(positions, types, is_solute, exclusions, box, sigma, epsilon, charg
     f = np.zeros((n, 3)) if forces else None
     g = np.zeros((3, sg.shape[0])) if param_grads else None
     npairs = np.zeros(1, np.int64)
+    absterms = np.zeros(NTERMS)
     rc = lib.oracle_eval(n, _ptr(pos), _ptr(t), _ptr(s), ex.shape[0], _ptr(ex), _ptr(bx), sg.shape[0], _ptr(sg),
                          _ptr(ep), _ptr(ch), params.cutoff, params.switch_width, params.dsf_alpha, params.sc_alpha,
-                         params.schedule, float(lam), _ptr(terms), _ptr(f), _ptr(g), _ptr(npairs), int(n_threads))
+                         params.schedule, float(lam), _ptr(terms), _ptr(f), _ptr(g), _ptr(npairs), _ptr(absterms),
+                         int(n_threads))
     if rc != 0:
         raise ValueError("oracle_eval rejected its input (code %d)" % rc)
-    out = dict(terms=terms, forces=f, n_pairs=int(npairs[0]))
+    out = dict(terms=terms, forces=f, n_pairs=int(npairs[0]), abs_terms=absterms)
     if param_grads:
         eps_t = ep
         with np.errstate(divide="ignore", invalid="ignore"):

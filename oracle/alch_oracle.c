@@ -287,7 +287,7 @@ int oracle_eval(int n, const double *pos, const int32_t *type, const uint8_t *is
                 const int32_t *excl, const double *box, int n_types, const double *sigma, const double *epsilon,
                 const double *charge, double cutoff, double switch_width, double dsf_alpha, double sc_alpha,
                 int schedule, double lambda, double *terms, double *forces, double *pgrad, int64_t *n_pairs,
-                int n_threads) {
+                double *abs_terms, int n_threads) {
   if (n < 0 || cutoff <= 0 || (schedule != SCHED_BEUTLER && schedule != SCHED_LBF)) return -1;
   for (int d = 0; d < 3; ++d)
     if (!(box[d] >= 2.0 * cutoff)) return -4;
@@ -310,6 +310,9 @@ int oracle_eval(int n, const double *pos, const int32_t *type, const uint8_t *is
 #endif
   /* per-thread accumulators, combined in thread order afterwards */
   enum { ACC_PLAIN_SOLV, ACC_PLAIN_SOLU, ACC_SS_VDW, ACC_SS_ELEC, ACC_UA, ACC_UB, ACC_DL_VDW, ACC_DL_ELEC, NACC };
+  /* sums of |pair contribution| per slot: the scale against which summed
+   * quantities with cancellation are compared */
+  double *absth = (double *)calloc((size_t)nt * NACC, sizeof(double));
   ksum *acc = (ksum *)calloc((size_t)nt * NACC, sizeof(ksum));
   double *fth = forces ? (double *)calloc((size_t)nt * 3 * (size_t)n, sizeof(double)) : NULL;
   double *gth = pgrad ? (double *)calloc((size_t)nt * 3 * (size_t)n_types, sizeof(double)) : NULL;
@@ -345,10 +348,18 @@ int oracle_eval(int n, const double *pos, const int32_t *type, const uint8_t *is
         pair_out o;
         eval_pair(r, sig, eps, qq, alch, &p, &ls, &o);
         cnt[tid]++;
+        double *ab = absth + (size_t)tid * NACC;
         if (!alch) {
           if (is_solute[i]) ks_add(&a[ACC_PLAIN_SOLU], o.u_plain);
           else ks_add(&a[ACC_PLAIN_SOLV], o.u_plain);
+          ab[is_solute[i] ? ACC_PLAIN_SOLU : ACC_PLAIN_SOLV] += fabs(o.u_plain);
         } else {
+          ab[ACC_SS_VDW] += fabs(o.ss_vdw);
+          ab[ACC_SS_ELEC] += fabs(o.ss_elec);
+          ab[ACC_UA] += fabs(o.ua);
+          ab[ACC_UB] += fabs(o.ub);
+          ab[ACC_DL_VDW] += fabs(o.dl_vdw);
+          ab[ACC_DL_ELEC] += fabs(o.dl_elec);
           ks_add(&a[ACC_SS_VDW], o.ss_vdw);
           ks_add(&a[ACC_SS_ELEC], o.ss_elec);
           ks_add(&a[ACC_UA], o.ua);
@@ -412,6 +423,16 @@ int oracle_eval(int n, const double *pos, const int32_t *type, const uint8_t *is
       for (int k = 0; k < 3 * n_types; ++k) pgrad[k] += gth[(size_t)t * 3 * n_types + k];
   }
   if (n_pairs) *n_pairs = npairs;
+  if (abs_terms) {
+    double ab[NACC];
+    memset(ab, 0, sizeof(ab));
+    for (int t = 0; t < nt; ++t)
+      for (int k = 0; k < NACC; ++k) ab[k] += absth[(size_t)t * NACC + k];
+    for (int k = 0; k < NACC; ++k) abs_terms[k] = ab[k];  /* slots 0-7 match the term slots */
+    abs_terms[T_TOTAL] = ab[ACC_PLAIN_SOLV] + ab[ACC_PLAIN_SOLU] + ab[ACC_SS_VDW] + ab[ACC_SS_ELEC];
+    abs_terms[T_DUDL] = ab[ACC_DL_VDW] + ab[ACC_DL_ELEC];
+  }
+  free(absth);
   free(w); free(acc); free(fth); free(gth); free(cnt); free(ix.start);
   return 0;
 }

@@ -1,0 +1,651 @@
+// Host side of libalchnb: the C ABI declared in include/alch_nb.h.
+//
+// alch_nb_create() does host-only work (validation, grid planning, list
+// capacity); alch_nb_bind() carves a caller-owned device workspace and
+// uploads the static tables; every other call enqueues kernels on the bound
+// stream and returns without waiting, except those documented as syncing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "alch_nb.h"
+#include "anb_internal.h"
+#include "anb_kernels.h"
+
+using namespace anb;
+
+namespace {
+
+struct Variant {
+  int epu, blocks, xcd;
+};
+// Launch variants of the tile kernel searched by alch_nb_autotune().
+const Variant kVariants[] = {
+    {8, 1024, 1}, {4, 2048, 1}, {16, 1024, 1}, {32, 512, 1}, {8, 1024, 0}, {8, 2048, 1}, {16, 2048, 1}, {2, 2048, 1},
+};
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+constexpr int kMinEpu = 2;
+constexpr int kTimingSlots = 4096;
+
+struct Carve {
+  size_t off = 0;
+  template <typename T>
+  T* take(char* base, size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * std::max<size_t>(count, 1);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct alch_nb_ctx {
+  // parameters
+  alch_nb_params p{};
+  std::vector<double> sigma, eps, charge;
+  int K = 0, N = 0, G = 0, C = 0, T = 0;
+  double r_list = 0;
+  // static tables (host copies)
+  std::vector<int> atom_type, atom_grid, grid_atoms, excl_start, excl_j, col_grid, atom_rep;
+  std::vector<GridInfo> grids;
+  std::vector<float4> tp32;
+  std::vector<double4> tp64;
+  std::vector<ReplicaInfo> reps;
+  int sc_cap = 0, ent_cap = 0, unit_cap = 0;
+  size_t ws_bytes = 0;
+  // bound state
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  Dev dev{};
+  PotConsts pc{};
+  int variant = 0;
+  hipError_t last_hip = hipSuccess;
+  unsigned long long* export_counter = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  int n_timed = 0;
+  double tile_ms = 0;
+  long long tile_launches = 0;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+static alch_nb_status hip_fail(alch_nb_ctx* c, hipError_t e) {
+  if (c) c->last_hip = e;
+  return ALCH_NB_E_HIP;
+}
+#define HIPCHK(call)                          \
+  do {                                        \
+    hipError_t e_ = (call);                   \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_); \
+  } while (0)
+
+// ------------------------------------------------------------------ planning
+
+static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
+  Carve cv;
+  const size_t N = ctx->N, C = ctx->C, SC = ctx->sc_cap, E = ctx->ent_cap, U = ctx->unit_cap, K = ctx->K;
+  const size_t SL = SC * kSc, CL = SC * kScCl;
+  d->n_atoms = ctx->N;
+  d->n_reps = ctx->K;
+  d->n_grids = ctx->G;
+  d->n_cols = ctx->C;
+  d->sc_cap = ctx->sc_cap;
+  d->ent_cap = ctx->ent_cap;
+  d->unit_cap = ctx->unit_cap;
+  d->n_types = ctx->T;
+  d->atom_type = cv.take<int>(base, N);
+  d->atom_grid = cv.take<int>(base, N);
+  d->grid_atoms = cv.take<int>(base, N);
+  d->grids = cv.take<GridInfo>(base, ctx->G);
+  d->reps = cv.take<ReplicaInfo>(base, K);
+  d->excl_start = cv.take<int>(base, N + 1);
+  d->excl_j = cv.take<int>(base, ctx->excl_j.size());
+  d->type_sigma = cv.take<double>(base, ctx->T);
+  d->type_eps = cv.take<double>(base, ctx->T);
+  d->type_q = cv.take<double>(base, ctx->T);
+  d->col_grid = cv.take<int>(base, C);
+  d->x_build = cv.take<double>(base, 3 * N);
+  d->xw = cv.take<double>(base, 3 * N);
+  d->atom_col = cv.take<int>(base, N);
+  d->col_count = cv.take<int>(base, C);
+  d->col_start = cv.take<int>(base, C);
+  d->col_fill = cv.take<int>(base, C);
+  d->col_sc = cv.take<int>(base, C);
+  d->col_nsc = cv.take<int>(base, C);
+  d->bucket = cv.take<int>(base, N);
+  d->sorted = cv.take<int>(base, N);
+  d->sc_first = cv.take<int>(base, SC);
+  d->sc_n = cv.take<int>(base, SC);
+  d->sc_col = cv.take<int>(base, SC);
+  d->sc_origin = cv.take<double>(base, 3 * SC);
+  d->sc_bbox = cv.take<double>(base, 6 * SC);
+  d->cl_bbox = cv.take<double>(base, 6 * CL);
+  d->cl_n = cv.take<int>(base, CL);
+  d->slot_atom = cv.take<int>(base, SL);
+  d->atom_slot = cv.take<int>(base, N);
+  d->se32 = cv.take<float2>(base, SL);
+  d->se64 = cv.take<double2>(base, SL);
+  d->q32 = cv.take<float>(base, SL);
+  d->q64 = cv.take<double>(base, SL);
+  d->sc_ecount = cv.take<int>(base, SC);
+  d->sc_estart = cv.take<int>(base, SC);
+  d->sc_ustart = cv.take<int>(base, SC);
+  d->ent_jc = cv.take<int>(base, E);
+  d->ent_info = cv.take<uint32_t>(base, E);
+  d->ent_isc = cv.take<int>(base, E);
+  d->ent_mask = cv.take<unsigned long long>(base, E * kScCl);
+  d->units = cv.take<int4>(base, U);
+  d->rep_ustart = cv.take<int>(base, K + 1);
+  d->ctr = cv.take<int>(base, 16);
+  d->flags = cv.take<unsigned int>(base, 1);
+  d->rebuild = cv.take<int>(base, 1);
+  d->pos32 = cv.take<float4>(base, SL);
+  d->pos64 = cv.take<double4>(base, SL);
+  d->ffix = cv.take<unsigned long long>(base, 3 * SL);
+  d->unit_acc = cv.take<double>(base, U * NACC);
+  d->lam = cv.take<LamState>(base, K);
+  d->pgrad_part = cv.take<double>(base, (size_t)kPgBlocks * 3 * ctx->T);
+  d->tp32 = cv.take<float4>(base, (size_t)ctx->T * ctx->T);
+  d->tp64 = cv.take<double4>(base, (size_t)ctx->T * ctx->T);
+  ctx->export_counter = cv.take<unsigned long long>(base, 1);
+  ctx->ws_bytes = cv.off + 256;
+}
+
+// Steiner volume of an a x b x c box grown by R.
+static double steiner(double a, double b, double c, double R) {
+  return a * b * c + 2.0 * (a * b + b * c + c * a) * R + M_PI * (a + b + c) * R * R + 4.0 / 3.0 * M_PI * R * R * R;
+}
+
+extern "C" {
+
+const char* alch_nb_strerror(alch_nb_status s) {
+  switch (s) {
+    case ALCH_NB_OK: return "ok";
+    case ALCH_NB_E_INVALID_ARG: return "invalid argument";
+    case ALCH_NB_E_BOX_TOO_SMALL: return "cutoff + skin exceeds half the shortest box edge";
+    case ALCH_NB_E_UNSUPPORTED: return "unsupported request";
+    case ALCH_NB_E_CAPACITY: return "neighbour list exceeds its capacity";
+    case ALCH_NB_E_HIP: return "HIP runtime error";
+    case ALCH_NB_E_NOT_BOUND: return "context has no workspace bound";
+    case ALCH_NB_E_NO_DEVICE: return "no usable GPU";
+    default: return "unknown status";
+  }
+}
+
+int32_t alch_nb_num_variants(void) { return kNumVariants; }
+
+double alch_nb_flops_per_pair(int32_t kind) {
+  // Algorithmic count of the pair evaluation (one add, multiply, compare,
+  // square root, exponential or error function = 1; see the design notes):
+  // displacement with image shift 6, r^2 5, cutoff test 1, 1/r, r, 1/r^2 3,
+  // combination rule 5, (sigma/r)^6 4, LJ energy and force 8, switch 15,
+  // switched LJ 4, DSF energy and force 18, force vector and both
+  // accumulations 11, energy accumulation 1 -> 81.  Solute-solvent pairs add
+  // the soft core (x, its derivatives, dU/dlambda): 24.
+  return kind == 0 ? 81.0 : 105.0;
+}
+
+alch_nb_status alch_nb_opes_layout(int32_t* offsets, int32_t n) {
+  // 0: theta, 1: lambda, 2: dlambda/dtheta, 3: U_opes, 4: dU_opes/dtheta,
+  // 5: F_theta, 6: kT, 7: sigma, 8: barrier_std, 9: barrier_expl,
+  // 10: n_deposited, 11: sum of Standard weights, 12..15 reserved,
+  // 16: rho_std[GRID], 16+GRID: rho_expl[GRID], 16+2 GRID: bias[GRID],
+  // 16+3 GRID: dbias[GRID]
+  const int32_t v[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 16, 16 + ALCH_NB_OPES_GRID, 16 + 2 * ALCH_NB_OPES_GRID,
+                       16 + 3 * ALCH_NB_OPES_GRID};
+  const int32_t m = (int32_t)(sizeof(v) / sizeof(v[0]));
+  if (!offsets || n < m) return ALCH_NB_E_INVALID_ARG;
+  for (int i = 0; i < m; ++i) offsets[i] = v[i];
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* sys, int32_t n_systems,
+                              alch_nb_ctx** out) {
+  if (!out) return ALCH_NB_E_INVALID_ARG;
+  *out = nullptr;
+  if (!prm || !sys || n_systems < 1) return ALCH_NB_E_INVALID_ARG;
+  const alch_nb_params& p = *prm;
+  if (p.n_types < 1 || !p.sigma || !p.epsilon || !p.charge) return ALCH_NB_E_INVALID_ARG;
+  if (!(p.cutoff > 0) || !(p.skin >= 0) || !(p.switch_width >= 0) || !(p.switch_width < p.cutoff) ||
+      !(p.dsf_alpha >= 0) || !(p.sc_alpha >= 0))
+    return ALCH_NB_E_INVALID_ARG;
+  if (p.schedule != ALCH_NB_BEUTLER_DSF && p.schedule != ALCH_NB_LBF_DSF) return ALCH_NB_E_INVALID_ARG;
+  if (p.precision != ALCH_NB_FP32_FIXED && p.precision != ALCH_NB_FP64) return ALCH_NB_E_INVALID_ARG;
+  if (p.variant < -1 || p.variant >= kNumVariants) return ALCH_NB_E_INVALID_ARG;
+  for (int t = 0; t < p.n_types; ++t)
+    if (!(p.sigma[t] > 0) || !(p.epsilon[t] >= 0) || !std::isfinite(p.charge[t])) return ALCH_NB_E_INVALID_ARG;
+  if (p.precision == ALCH_NB_FP32_FIXED && p.dsf_alpha * p.cutoff > 4.0) return ALCH_NB_E_UNSUPPORTED;
+  const double r_list = p.cutoff + p.skin;
+  long long n_total = 0;
+  for (int k = 0; k < n_systems; ++k) {
+    const alch_nb_system& s = sys[k];
+    if (s.n_atoms < 0 || s.n_excl < 0) return ALCH_NB_E_INVALID_ARG;
+    if (s.n_atoms > 0 && (!s.type || !s.is_solute)) return ALCH_NB_E_INVALID_ARG;
+    if (s.n_excl > 0 && !s.excl) return ALCH_NB_E_INVALID_ARG;
+    for (int d = 0; d < 3; ++d)
+      if (!(s.box[d] > 0) || !std::isfinite(s.box[d])) return ALCH_NB_E_INVALID_ARG;
+    for (int i = 0; i < s.n_atoms; ++i) {
+      if (s.type[i] < 0 || s.type[i] >= p.n_types) return ALCH_NB_E_INVALID_ARG;
+      if (s.is_solute[i] > 1) return ALCH_NB_E_INVALID_ARG;
+    }
+    for (int e = 0; e < s.n_excl; ++e) {
+      const int i = s.excl[2 * e], j = s.excl[2 * e + 1];
+      if (i < 0 || j <= i || j >= s.n_atoms) return ALCH_NB_E_INVALID_ARG;
+      if (e > 0) {
+        const int pi = s.excl[2 * e - 2], pj = s.excl[2 * e - 1];
+        if (i < pi || (i == pi && j <= pj)) return ALCH_NB_E_INVALID_ARG;
+      }
+    }
+    n_total += s.n_atoms;
+  }
+  if (n_total > (1 << 28)) return ALCH_NB_E_UNSUPPORTED;
+  for (int k = 0; k < n_systems; ++k)
+    for (int d = 0; d < 3; ++d)
+      if (sys[k].n_atoms > 0 && r_list > 0.5 * sys[k].box[d]) return ALCH_NB_E_BOX_TOO_SMALL;
+
+  alch_nb_ctx* ctx = new (std::nothrow) alch_nb_ctx();
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  ctx->p = p;
+  ctx->T = p.n_types;
+  ctx->sigma.assign(p.sigma, p.sigma + p.n_types);
+  ctx->eps.assign(p.epsilon, p.epsilon + p.n_types);
+  ctx->charge.assign(p.charge, p.charge + p.n_types);
+  ctx->p.sigma = ctx->sigma.data();
+  ctx->p.epsilon = ctx->eps.data();
+  ctx->p.charge = ctx->charge.data();
+  ctx->K = n_systems;
+  ctx->N = (int)n_total;
+  ctx->r_list = r_list;
+  ctx->variant = p.variant < 0 ? 0 : p.variant;
+
+  // per-atom tables, exclusion CSR (global indices)
+  ctx->atom_type.resize(n_total);
+  ctx->atom_grid.resize(n_total);
+  ctx->atom_rep.resize(n_total);
+  ctx->excl_start.assign(n_total + 1, 0);
+  {
+    int off = 0;
+    for (int k = 0; k < n_systems; ++k) {
+      const alch_nb_system& s = sys[k];
+      for (int i = 0; i < s.n_atoms; ++i) {
+        ctx->atom_type[off + i] = s.type[i];
+        ctx->atom_rep[off + i] = k;
+      }
+      for (int e = 0; e < s.n_excl; ++e) ctx->excl_start[off + s.excl[2 * e] + 1]++;
+      off += s.n_atoms;
+    }
+    for (int i = 0; i < ctx->N; ++i) ctx->excl_start[i + 1] += ctx->excl_start[i];
+    ctx->excl_j.resize(ctx->excl_start[ctx->N]);
+    off = 0;
+    std::vector<int> fill(ctx->excl_start.begin(), ctx->excl_start.end() - 1);
+    for (int k = 0; k < n_systems; ++k) {
+      const alch_nb_system& s = sys[k];
+      for (int e = 0; e < s.n_excl; ++e) ctx->excl_j[fill[off + s.excl[2 * e]]++] = off + s.excl[2 * e + 1];
+      off += s.n_atoms;
+    }
+  }
+
+  // grids: per box, the solute group then the environment group
+  const double margin = 1.0;  // position jitter allowance in the cluster size estimate
+  double ent_est = 0;
+  int atom_off = 0, col_base = 0, sc_base = 0;
+  for (int k = 0; k < n_systems; ++k) {
+    const alch_nb_system& s = sys[k];
+    ReplicaInfo rp{};
+    for (int d = 0; d < 3; ++d) rp.box[d] = s.box[d];
+    rp.atom_off = atom_off;
+    rp.n_atoms = s.n_atoms;
+    rp.grid0 = (int)ctx->grids.size();
+    rp.n_grids = 2;
+    rp.sc_begin = sc_base;
+    const double V = s.box[0] * s.box[1] * s.box[2];
+    const double rho_all = s.n_atoms > 0 ? s.n_atoms / V : 0.0;
+    int sc_of_grid[2] = {0, 0};
+    double ext[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    for (int grp = 1; grp >= 0; --grp) {  // solute (1) first
+      GridInfo g{};
+      g.replica = k;
+      g.is_solute = grp;
+      g.atom_off = (int)ctx->grid_atoms.size();
+      for (int i = 0; i < s.n_atoms; ++i)
+        if ((int)s.is_solute[i] == grp) {
+          ctx->grid_atoms.push_back(atom_off + i);
+          ctx->atom_grid[atom_off + i] = (int)ctx->grids.size();
+        }
+      g.n_atoms = (int)ctx->grid_atoms.size() - g.atom_off;
+      int ncx = 1, ncy = 1;
+      if (g.n_atoms > 512 || (grp == 0 && g.n_atoms > 0)) {
+        const double rho = g.n_atoms / V;
+        const double b = std::cbrt(kSc / rho);
+        ncx = std::max(1, (int)std::floor(s.box[0] / b));
+        ncy = std::max(1, (int)std::floor(s.box[1] / b));
+        ncx = std::min(ncx, 4096);
+        ncy = std::min(ncy, 4096);
+      }
+      g.ncx = ncx;
+      g.ncy = ncy;
+      g.wx = s.box[0] / ncx;
+      g.wy = s.box[1] / ncy;
+      g.col_base = col_base;
+      g.sc_base = sc_base;
+      g.sc_cap = g.n_atoms > 0 ? (g.n_atoms + kSc - 1) / kSc + ncx * ncy : 0;
+      for (int c = 0; c < ncx * ncy; ++c) ctx->col_grid.push_back((int)ctx->grids.size());
+      col_base += ncx * ncy;
+      sc_base += g.sc_cap;
+      sc_of_grid[grp] = g.sc_cap;
+      if (g.n_atoms > 0) {
+        const double rho = std::max(g.n_atoms / V, 1e-12);
+        ext[grp][0] = std::min(g.wx, s.box[0]);
+        ext[grp][1] = std::min(g.wy, s.box[1]);
+        ext[grp][2] = std::min(s.box[2], kSc / (rho * g.wx * g.wy)) + margin;
+      }
+      ctx->grids.push_back(g);
+    }
+    rp.sc_end = sc_base;
+    ctx->reps.push_back(rp);
+    atom_off += s.n_atoms;
+    // entry estimate: j-clusters within r_list of each SC box (cluster
+    // density of the whole box), half of them for the half list, full for the
+    // solute SCs whose partners all come later
+    if (s.n_atoms > 0) {
+      const double a_cl = std::cbrt(kCl / rho_all);
+      const double R = r_list + 0.9 * a_cl + margin;
+      const double rho_cl = rho_all / kCl * 1.25;  // padding allowance
+      for (int grp = 0; grp < 2; ++grp) {
+        if (sc_of_grid[grp] == 0) continue;
+        const double per_sc = rho_cl * steiner(ext[grp][0], ext[grp][1], ext[grp][2], R);
+        ent_est += sc_of_grid[grp] * per_sc * (grp == 1 ? 1.0 : 0.5);
+      }
+    }
+  }
+  ctx->G = (int)ctx->grids.size();
+  ctx->C = (int)ctx->col_grid.size();
+  ctx->sc_cap = std::max(1, sc_base);
+  const double fac = p.list_capacity_factor > 0 ? p.list_capacity_factor : 1.0;
+  const double ent_cap = std::ceil(fac * (1.6 * ent_est + 64.0 * ctx->sc_cap + 1024.0));
+  if (ent_cap > 2.0e9 / kScCl) {
+    delete ctx;
+    return ALCH_NB_E_UNSUPPORTED;
+  }
+  ctx->ent_cap = (int)ent_cap;
+  ctx->unit_cap = ctx->ent_cap / kMinEpu + ctx->sc_cap + 1;
+
+  // potential constants (FP64)
+  PotConsts& pc = ctx->pc;
+  pc.rc = p.cutoff;
+  pc.rc2 = p.cutoff * p.cutoff;
+  pc.rs = p.cutoff - p.switch_width;
+  pc.inv_w = p.switch_width > 0 ? 1.0 / p.switch_width : 0.0;
+  pc.alpha = p.dsf_alpha;
+  const double ec = std::erfc(p.dsf_alpha * p.cutoff);
+  pc.A = ec / p.cutoff;
+  pc.c2a = 2.0 * p.dsf_alpha / std::sqrt(M_PI);
+  pc.B = ec / (p.cutoff * p.cutoff) + pc.c2a * std::exp(-p.dsf_alpha * p.dsf_alpha * p.cutoff * p.cutoff) / p.cutoff;
+  pc.sc_alpha = p.sc_alpha;
+  // type-pair table in FP64: sigma_ij, 4 eps_ij, k_e q_i q_j, 1/sigma_ij^6
+  ctx->tp32.resize((size_t)ctx->T * ctx->T);
+  ctx->tp64.resize((size_t)ctx->T * ctx->T);
+  for (int a = 0; a < ctx->T; ++a)
+    for (int b = 0; b < ctx->T; ++b) {
+      const double sg = 0.5 * (ctx->sigma[a] + ctx->sigma[b]);
+      const double e4 = 4.0 * std::sqrt(ctx->eps[a] * ctx->eps[b]);
+      const double qq = kKe * ctx->charge[a] * ctx->charge[b];
+      const double is6 = 1.0 / (sg * sg * sg * sg * sg * sg);
+      ctx->tp64[(size_t)a * ctx->T + b] = make_double4(sg, e4, qq, is6);
+      ctx->tp32[(size_t)a * ctx->T + b] = make_float4((float)sg, (float)e4, (float)qq, (float)is6);
+    }
+  lay_out(ctx, nullptr, &ctx->dev);
+  *out = ctx;
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_workspace_size(const alch_nb_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return ALCH_NB_E_INVALID_ARG;
+  *bytes = ctx->ws_bytes;
+  return ALCH_NB_OK;
+}
+
+static void destroy_graph(alch_nb_ctx* ctx) {
+  if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) hipGraphDestroy(ctx->graph);
+  ctx->gexec = nullptr;
+  ctx->graph = nullptr;
+}
+
+alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* stream) {
+  if (!ctx || !d_ws) return ALCH_NB_E_INVALID_ARG;
+  if (bytes < ctx->ws_bytes || (reinterpret_cast<uintptr_t>(d_ws) & 255u)) return ALCH_NB_E_INVALID_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ALCH_NB_E_NO_DEVICE;
+  destroy_graph(ctx);
+  ctx->ws = reinterpret_cast<char*>(d_ws);
+  ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  lay_out(ctx, ctx->ws, &ctx->dev);
+  Dev& d = ctx->dev;
+  hipStream_t st = ctx->stream;
+  auto up = [&](const void* dst, const void* src, size_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    return hipMemcpyAsync(const_cast<void*>(dst), src, n, hipMemcpyHostToDevice, st);
+  };
+  HIPCHK(up(d.atom_type, ctx->atom_type.data(), sizeof(int) * ctx->N));
+  HIPCHK(up(d.atom_grid, ctx->atom_grid.data(), sizeof(int) * ctx->N));
+  HIPCHK(up(d.grid_atoms, ctx->grid_atoms.data(), sizeof(int) * ctx->grid_atoms.size()));
+  HIPCHK(up(d.grids, ctx->grids.data(), sizeof(GridInfo) * ctx->G));
+  HIPCHK(up(d.reps, ctx->reps.data(), sizeof(ReplicaInfo) * ctx->K));
+  HIPCHK(up(d.excl_start, ctx->excl_start.data(), sizeof(int) * (ctx->N + 1)));
+  HIPCHK(up(d.excl_j, ctx->excl_j.data(), sizeof(int) * ctx->excl_j.size()));
+  HIPCHK(up(d.type_sigma, ctx->sigma.data(), sizeof(double) * ctx->T));
+  HIPCHK(up(d.type_eps, ctx->eps.data(), sizeof(double) * ctx->T));
+  HIPCHK(up(d.type_q, ctx->charge.data(), sizeof(double) * ctx->T));
+  HIPCHK(up(d.col_grid, ctx->col_grid.data(), sizeof(int) * ctx->C));
+  HIPCHK(up(d.tp32, ctx->tp32.data(), sizeof(float4) * ctx->tp32.size()));
+  HIPCHK(up(d.tp64, ctx->tp64.data(), sizeof(double4) * ctx->tp64.size()));
+  HIPCHK(launch_init(d, st));
+  // the host copies must outlive the asynchronous uploads
+  HIPCHK(hipStreamSynchronize(st));
+  if (ctx->ev.empty()) {
+    ctx->ev.resize(2 * kTimingSlots);
+    for (auto& e : ctx->ev) HIPCHK(hipEventCreate(&e));
+  }
+  ctx->bound = true;
+  return ALCH_NB_OK;
+}
+
+static TileShape shape_of(const alch_nb_ctx* ctx) {
+  const Variant& v = kVariants[ctx->variant];
+  TileShape s;
+  s.epu = v.epu;
+  s.xcd = v.xcd;
+  const long long need = ((long long)ctx->unit_cap + 3) / 4;
+  long long b = std::min<long long>(v.blocks, std::max<long long>(8, need));
+  b = (b + 7) / 8 * 8;
+  s.blocks = (int)b;
+  return s;
+}
+
+static alch_nb_status enqueue_compute(alch_nb_ctx* ctx, const double* pos, const double* lam, uint32_t flags,
+                                      const alch_nb_out* out, bool allow_timing) {
+  const alch_nb_params& p = ctx->p;
+  int mode = 0;
+  if (flags & ALCH_NB_FORCE_REBUILD) mode = 2;
+  else if (flags & ALCH_NB_AUTO_REBUILD) mode = p.skin > 0 ? 1 : 2;
+  const TileShape sh = shape_of(ctx);
+  const Dev& d = ctx->dev;
+  hipStream_t st = ctx->stream;
+  HIPCHK(launch_prepare(d, st, pos, lam, mode, 0.5 * p.skin, p.schedule));
+  HIPCHK(launch_list_build(d, st, pos, ctx->r_list, sh.epu));
+  HIPCHK(launch_canon(d, st, pos, p.precision));
+  const bool timed = allow_timing && ctx->timing && ctx->n_timed < kTimingSlots;
+  if (timed) HIPCHK(hipEventRecord(ctx->ev[2 * ctx->n_timed], st));
+  HIPCHK(launch_tile(d, st, ctx->pc, p.precision, p.schedule, sh, pos));
+  if (timed) {
+    HIPCHK(hipEventRecord(ctx->ev[2 * ctx->n_timed + 1], st));
+    ctx->n_timed++;
+  }
+  HIPCHK(launch_finalize(d, st, p.precision, p.schedule, out ? out->terms : nullptr, out ? out->forces : nullptr,
+                         out ? out->dudl : nullptr, out ? reinterpret_cast<long long*>(out->n_pairs) : nullptr));
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_compute(alch_nb_ctx* ctx, const double* d_pos, const double* d_lambda, uint32_t flags,
+                               const alch_nb_out* out) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!d_pos || !d_lambda) return ALCH_NB_E_INVALID_ARG;
+  return enqueue_compute(ctx, d_pos, d_lambda, flags, out, true);
+}
+
+alch_nb_status alch_nb_build_list(alch_nb_ctx* ctx, const double* d_pos) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!d_pos) return ALCH_NB_E_INVALID_ARG;
+  const Dev& d = ctx->dev;
+  HIPCHK(launch_prepare(d, ctx->stream, d_pos, nullptr, 2, 0.5 * ctx->p.skin, ctx->p.schedule));
+  HIPCHK(launch_list_build(d, ctx->stream, d_pos, ctx->r_list, shape_of(ctx).epu));
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_set_variant(alch_nb_ctx* ctx, int32_t variant) {
+  if (!ctx || variant < 0 || variant >= kNumVariants) return ALCH_NB_E_INVALID_ARG;
+  const int old_epu = kVariants[ctx->variant].epu;
+  ctx->variant = variant;
+  destroy_graph(ctx);
+  if (ctx->bound && kVariants[variant].epu != old_epu) HIPCHK(launch_units(ctx->dev, ctx->stream, kVariants[variant].epu));
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_set_timing(alch_nb_ctx* ctx, int32_t enable) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  ctx->timing = enable != 0;
+  return ALCH_NB_OK;
+}
+
+static alch_nb_status collect_timing(alch_nb_ctx* ctx) {
+  for (int i = 0; i < ctx->n_timed; ++i) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]));
+    ctx->tile_ms += ms;
+    ctx->tile_launches++;
+  }
+  ctx->n_timed = 0;
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_get_flags(alch_nb_ctx* ctx, uint32_t* flags) {
+  if (!ctx || !flags) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  unsigned int f = 0;
+  HIPCHK(hipMemcpyAsync(&f, ctx->dev.flags, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->dev.flags, 0, sizeof(unsigned int), ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *flags = f;
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_get_stats(alch_nb_ctx* ctx, alch_nb_stats* s) {
+  if (!ctx || !s) return ALCH_NB_E_INVALID_ARG;
+  std::memset(s, 0, sizeof(*s));
+  s->n_atoms = ctx->N;
+  s->n_systems = ctx->K;
+  s->entry_capacity = ctx->ent_cap;
+  s->unit_capacity = ctx->unit_cap;
+  s->variant = ctx->variant;
+  const TileShape sh = shape_of(ctx);
+  s->entries_per_unit = sh.epu;
+  s->blocks = sh.blocks;
+  if (!ctx->bound) return ALCH_NB_OK;
+  int c[16];
+  HIPCHK(hipMemcpyAsync(c, ctx->dev.ctr, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  alch_nb_status r = collect_timing(ctx);
+  if (r != ALCH_NB_OK) return r;
+  s->n_entries = c[CTR_ENT_NEED];
+  s->n_units = c[CTR_UNIT_NEED];
+  s->n_rebuilds = c[CTR_NBUILD];
+  s->n_superclusters = ctx->sc_cap;
+  s->tile_ms_total = ctx->tile_ms;
+  s->tile_launches_timed = ctx->tile_launches;
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_export_pairs(alch_nb_ctx* ctx, int32_t* d_pairs, int64_t cap, int64_t* n_out) {
+  if (!ctx || !n_out || cap < 0 || (cap > 0 && !d_pairs)) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  HIPCHK(hipMemsetAsync(ctx->export_counter, 0, sizeof(unsigned long long), ctx->stream));
+  HIPCHK(launch_export(ctx->dev, ctx->stream, ctx->r_list, d_pairs, cap, ctx->export_counter));
+  unsigned long long n = 0;
+  HIPCHK(hipMemcpyAsync(&n, ctx->export_counter, sizeof(n), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  *n_out = (int64_t)n;
+  return (int64_t)n > cap ? ALCH_NB_E_CAPACITY : ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_capture_step(alch_nb_ctx* ctx, const double* d_pos, const double* d_lambda,
+                                    const alch_nb_out* out) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!d_pos || !d_lambda) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->stream) return ALCH_NB_E_UNSUPPORTED;  // capture needs a non-null stream
+  destroy_graph(ctx);
+  HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  alch_nb_status r = enqueue_compute(ctx, d_pos, d_lambda, ALCH_NB_AUTO_REBUILD, out, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+  if (r != ALCH_NB_OK) {
+    if (g) hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e);
+  ctx->graph = g;
+  HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_launch_step(alch_nb_ctx* ctx) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->gexec) return ALCH_NB_E_NOT_BOUND;
+  HIPCHK(hipGraphLaunch(ctx->gexec, ctx->stream));
+  return ALCH_NB_OK;
+}
+
+int32_t alch_nb_last_hip_error(const alch_nb_ctx* ctx) { return ctx ? (int32_t)ctx->last_hip : 0; }
+
+void alch_nb_destroy(alch_nb_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->bound && ctx->stream) hipStreamSynchronize(ctx->stream);
+  destroy_graph(ctx);
+  for (auto& e : ctx->ev) hipEventDestroy(e);
+  delete ctx;
+}
+
+// ------------------------------------------------------------------ not yet
+alch_nb_status alch_nb_backward(alch_nb_ctx* ctx, const double*, const double*, const double*, const alch_nb_grad*) {
+  return ctx ? ALCH_NB_E_UNSUPPORTED : ALCH_NB_E_INVALID_ARG;
+}
+alch_nb_status alch_nb_dihedrals(alch_nb_ctx* ctx, const double*, int32_t, const int32_t*, double*, double*,
+                                 const double*, double*, const double*, const double*, double*, double*) {
+  return ctx ? ALCH_NB_E_UNSUPPORTED : ALCH_NB_E_INVALID_ARG;
+}
+alch_nb_status alch_nb_opes_update(alch_nb_ctx* ctx, double*, const double*, double*, int32_t) {
+  return ctx ? ALCH_NB_E_UNSUPPORTED : ALCH_NB_E_INVALID_ARG;
+}
+alch_nb_status alch_nb_autotune(alch_nb_ctx* ctx, const double*, const double*, int32_t) {
+  return ctx ? ALCH_NB_E_UNSUPPORTED : ALCH_NB_E_INVALID_ARG;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Internal layout shared by the host side and the HIP kernels of libalchnb.
+//
+// Spatial organisation (per box, per group: the solute atoms and the
+// environment atoms of a box each get their own column grid so that no
+// cluster mixes the two groups):
+//   column  - an x-y cell of the group's grid spanning the whole box in z;
+//   super-cluster (SC) - 64 consecutive z-sorted atoms of one column, split
+//             2 x 2 x 2 into 8 clusters (fewer if the column runs out);
+//   cluster - 8 atom slots; empty slots are padding.
+// A list entry pairs one i-SC with one j-cluster and one periodic image
+// shift; an 8-bit mask says which of the SC's clusters interact with it and
+// eight 64-bit masks give the atom pairs (padding, exclusions, i<j inside a
+// cluster).  A work unit is a run of consecutive entries of one i-SC.
+#pragma once
+#include <stdint.h>
+
+namespace anb {
+
+constexpr int kCl = 8;           // atom slots per cluster
+constexpr int kScCl = 8;         // clusters per super-cluster
+constexpr int kSc = 64;          // atom slots per super-cluster
+constexpr double kKe = 332.06371;
+constexpr int kNTerms = 10;  // energy-term slots per box
+
+// per-unit energy accumulators (FP64)
+enum { ACC_SOLV = 0, ACC_SOLU = 1, ACC_A0 = 2, ACC_A1 = 3, ACC_A2 = 4, ACC_NPAIR = 5, NACC = 6 };
+// entry kinds
+enum { KIND_SOLV = 0, KIND_SOLU = 1, KIND_ALCH = 2 };
+
+struct GridInfo {
+  int replica, is_solute;
+  int atom_off, n_atoms;   // range in grid_atoms[]
+  int col_base, ncx, ncy;  // columns [col_base, col_base + ncx*ncy)
+  int sc_base, sc_cap;     // super-cluster slots [sc_base, sc_base + sc_cap)
+  int pad_;
+  double wx, wy;           // column widths
+};
+
+struct ReplicaInfo {
+  double box[3];
+  int atom_off, n_atoms;
+  int grid0, n_grids;
+  int sc_begin, sc_end;    // SC slot range of the replica
+};
+
+// Per-replica lambda factors, recomputed on the device every call.
+//   Beutler: a[0] = lv, a[1] = le, a[2] = dlv/dlambda, a[3] = dle/dlambda
+//   LBF:     a[0] = hA, a[1] = hB, a[2] = dhA, a[3] = dhB
+struct LamState {
+  double a[4];
+  float f[4];
+};
+
+// Entry info word: bits 0-7 i-cluster mask, 8-9 kind, 16-20 shift code
+// (sx+1) + 3 (sy+1) + 9 (sz+1).
+__host__ __device__ inline uint32_t ent_pack(uint32_t imask, uint32_t kind, uint32_t shift) {
+  return imask | (kind << 8) | (shift << 16);
+}
+
+// Device view of the workspace.
+struct Dev {
+  int n_atoms, n_reps, n_grids, n_cols, sc_cap, ent_cap, unit_cap, n_types;
+  // static tables
+  const int* atom_type;      // [N]
+  const int* atom_grid;      // [N]
+  const int* grid_atoms;     // [N] atoms of each grid, concatenated
+  const GridInfo* grids;     // [G]
+  const ReplicaInfo* reps;   // [K]
+  const int* excl_start;     // [N+1]
+  const int* excl_j;         // [M] global, sorted per row
+  const double* type_sigma;  // [T]
+  const double* type_eps;    // [T]
+  const double* type_q;      // [T]
+  int* col_grid;             // [C] grid of each column
+  // list state
+  double* x_build;           // [N*3]
+  double* xw;                // [N*3] wrapped positions at build
+  int* atom_col;             // [N]
+  int* col_count;            // [C]
+  int* col_start;            // [C]
+  int* col_fill;             // [C]
+  int* col_sc;               // [C] first SC of the column
+  int* col_nsc;              // [C]
+  int* bucket;               // [N]
+  int* sorted;               // [N]
+  int* sc_first;             // [SC] offset into sorted
+  int* sc_n;                 // [SC] atoms
+  int* sc_col;               // [SC]
+  double* sc_origin;         // [SC*3]
+  double* sc_bbox;           // [SC*6] lo xyz, hi xyz
+  double* cl_bbox;           // [SC*8*6]
+  int* cl_n;                 // [SC*8]
+  int* slot_atom;            // [SC*64] atom index or -1
+  int* atom_slot;            // [N]
+  float2* se32;              // [SC*64] sigma/2, 2 sqrt(eps)
+  double2* se64;             // [SC*64]
+  float* q32;                // [SC*64] q sqrt(k_e)
+  double* q64;               // [SC*64]
+  int* sc_ecount;            // [SC]
+  int* sc_estart;            // [SC]
+  int* sc_ustart;            // [SC]
+  int* ent_jc;               // [E]
+  uint32_t* ent_info;        // [E]
+  int* ent_isc;              // [E]
+  unsigned long long* ent_mask;  // [E*8]
+  int4* units;               // [U] sc, e0, e1, replica
+  int* rep_ustart;           // [K+1]
+  int* ctr;                  // [16] counters, see CTR_*
+  unsigned int* flags;       // [1] sticky flags
+  int* rebuild;              // [1]
+  // per call
+  float4* pos32;             // [SC*64] local x, y, z, q
+  double4* pos64;            // [SC*64]
+  unsigned long long* ffix;  // [3*SC*64] fixed-point forces, component-major
+  double* unit_acc;          // [U*NACC]
+  LamState* lam;             // [K]
+  double* pgrad_part;        // [PG_BLOCKS*3*T] parameter-gradient partials
+  const float4* tp32;        // [T*T] type-pair sigma, 4 eps, k_e q q, 1/sigma^6 (rounded from FP64)
+  const double4* tp64;       // [T*T]
+};
+
+enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5 };
+
+constexpr int kPgBlocks = 512;  // blocks of the parameter-gradient pass
+
+}  // namespace anb

@@ -1,0 +1,47 @@
+// Launchers of the HIP kernels (host side of libalchnb).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "anb_internal.h"
+
+namespace anb {
+
+// Pair-potential constants, precomputed on the host in FP64.
+struct PotConsts {
+  double rc, rc2, rs, inv_w;   // cutoff, its square, switch start, 1/width (0 = no switch)
+  double alpha, A, B, c2a;     // DSF: a, erfc(a rc)/rc, slope, 2a/sqrt(pi)
+  double sc_alpha;             // Beutler soft-core alpha
+};
+
+struct TileShape {
+  int epu;      // entries per work unit
+  int blocks;   // blocks of 256 threads (4 waves)
+  int xcd;      // 1 = XCD-aware unit mapping
+};
+
+hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, double r_list, int epu);
+hipError_t launch_units(const Dev& d, hipStream_t st, int epu);
+hipError_t launch_export(const Dev& d, hipStream_t st, double r_list, int* out, long long cap,
+                         unsigned long long* counter);
+hipError_t launch_init(const Dev& d, hipStream_t st);
+hipError_t launch_prepare(const Dev& d, hipStream_t st, const double* pos, const double* lambda, int mode,
+                          double half_skin, int schedule);
+hipError_t launch_canon(const Dev& d, hipStream_t st, const double* pos, int precision);
+hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
+                       const TileShape& shape, const double* xin);
+hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int schedule, double* terms,
+                           double* forces, double* dudl, long long* n_pairs);
+hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
+                              const double* g_energy, const TileShape& shape);
+hipError_t launch_backward_finish(const Dev& d, hipStream_t st, int precision, const double* g_energy,
+                                  const double* dudl_saved, const double* forces_saved, double* d_pos,
+                                  double* d_lambda, double* d_sigma, double* d_sqrt_eps, double* d_charge);
+hipError_t launch_dihedrals(hipStream_t st, const double* pos, int n_cv, const int* idx, double* xi, double* dxi,
+                            const double* mass_inv, double* msum, const double* s, const double* kappa,
+                            double* u_dafed, double* forces, const ReplicaInfo* reps, const int* atom_rep);
+hipError_t launch_opes(hipStream_t st, double* state, const double* dudl, double* lambda_out, int deposit);
+
+// Fixed-point scale of the force accumulators (units per kcal/mol/A).
+inline double fixed_scale(int precision) { return precision == 0 ? 4294967296.0 : 1099511627776.0; }
+
+}  // namespace anb

@@ -1,0 +1,153 @@
+"""Host-side contract of the C ABI (no GPU needed): symbols, validation, planning."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2608_12691_amd import alchnb, build
+    if not os.path.exists(alchnb.LIB_PATH):
+        build.build(force=True)
+    return alchnb.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "alch_nb.h")).read()
+    pat = r"^\s*(?:alch_nb_status|void|const char\s*\*|int32_t|double)\s*\*?\s*(alch_nb_[a-z0-9_]+)\s*\("
+    return sorted(set(re.findall(pat, src, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2608_12691_amd import alchnb
+    assert sorted(alchnb.EXPORTED) == names
+
+
+def _params(alchnb, ff, **kw):
+    p = alchnb.Params_t()
+    sig = np.ascontiguousarray(ff["sigma"], np.float64)
+    eps = np.ascontiguousarray(ff["epsilon"], np.float64)
+    chg = np.ascontiguousarray(ff["charge"], np.float64)
+    p.n_types = len(sig)
+    p.sigma, p.epsilon, p.charge = sig.ctypes.data, eps.ctypes.data, chg.ctypes.data
+    p.cutoff, p.skin, p.switch_width, p.dsf_alpha, p.sc_alpha = 9.0, 0.0, 1.0, 0.2, 0.5
+    p.schedule, p.precision, p.variant, p.list_capacity_factor = 0, 0, -1, 1.0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p, (sig, eps, chg)
+
+
+def _system(alchnb, n=4, box=20.0, types=None, sol=None, excl=None):
+    s = alchnb.System_t()
+    t = np.ascontiguousarray(types if types is not None else np.zeros(n), np.int32)
+    so = np.ascontiguousarray(sol if sol is not None else np.zeros(n), np.uint8)
+    ex = np.ascontiguousarray(excl if excl is not None else np.zeros((0, 2)), np.int32).reshape(-1, 2)
+    s.n_atoms = len(t)
+    s.type, s.is_solute = t.ctypes.data, so.ctypes.data
+    s.n_excl = ex.shape[0]
+    s.excl = ex.ctypes.data if ex.shape[0] else None
+    for d in range(3):
+        s.box[d] = box
+    return s, (t, so, ex)
+
+
+FF = dict(sigma=[3.0, 3.2], epsilon=[0.1, 0.0], charge=[0.4, -0.4])
+
+
+def _create(lib, p, systems):
+    from paper_2608_12691_amd import alchnb
+    arr = (alchnb.System_t * len(systems))(*systems)
+    ctx = ctypes.c_void_p()
+    st = lib.alch_nb_create(ctypes.byref(p), arr, len(systems), ctypes.byref(ctx))
+    return st, ctx
+
+
+def test_create_plans_workspace(lib):
+    from paper_2608_12691_amd import alchnb
+    p, keep = _params(alchnb, FF)
+    s, k2 = _system(alchnb, 6, 20.0, types=[0, 1, 0, 1, 0, 1], sol=[1, 0, 0, 0, 0, 0], excl=[[0, 1], [2, 3]])
+    st, ctx = _create(lib, p, [s])
+    assert st == 0 and ctx.value
+    nb = ctypes.c_size_t()
+    assert lib.alch_nb_workspace_size(ctx, ctypes.byref(nb)) == 0 and nb.value > 0
+    stats = alchnb.Stats_t()
+    assert lib.alch_nb_get_stats(ctx, ctypes.byref(stats)) == 0
+    assert stats.n_atoms == 6 and stats.entry_capacity > 0
+    # computing before binding is refused without touching the GPU
+    assert lib.alch_nb_compute(ctx, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, None) == 6
+    assert lib.alch_nb_build_list(ctx, ctypes.c_void_p(8)) == 6
+    lib.alch_nb_destroy(ctx)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("cutoff", -1.0, 1), ("skin", -0.5, 1), ("switch_width", 9.5, 1), ("schedule", 5, 1), ("precision", 3, 1),
+    ("variant", 99, 1), ("cutoff", 10.5, 2), ("dsf_alpha", 0.6, 3),
+])
+def test_create_rejects_bad_params(lib, field, value, code):
+    from paper_2608_12691_amd import alchnb
+    p, keep = _params(alchnb, FF, **{field: value})
+    s, k2 = _system(alchnb)
+    st, ctx = _create(lib, p, [s])
+    assert st == code
+    assert not ctx.value
+
+
+@pytest.mark.parametrize("kw", [
+    dict(types=[0, 1, 2, 0]),                       # type out of range
+    dict(sol=[0, 2, 0, 0]),                         # solute flag not 0/1
+    dict(excl=[[1, 0]]),                            # i > j
+    dict(excl=[[0, 2], [0, 1]]),                    # unsorted
+    dict(excl=[[0, 1], [0, 1]]),                    # duplicate
+    dict(excl=[[0, 7]]),                            # out of range
+])
+def test_create_rejects_bad_systems(lib, kw):
+    from paper_2608_12691_amd import alchnb
+    p, keep = _params(alchnb, FF)
+    s, k2 = _system(alchnb, **kw)
+    st, ctx = _create(lib, p, [s])
+    assert st == 1
+
+
+def test_create_rejects_null_and_empty(lib):
+    from paper_2608_12691_amd import alchnb
+    p, keep = _params(alchnb, FF)
+    ctx = ctypes.c_void_p()
+    assert lib.alch_nb_create(None, None, 1, ctypes.byref(ctx)) == 1
+    assert lib.alch_nb_create(ctypes.byref(p), None, 1, ctypes.byref(ctx)) == 1
+    s, k2 = _system(alchnb)
+    arr = (alchnb.System_t * 1)(s)
+    assert lib.alch_nb_create(ctypes.byref(p), arr, 0, ctypes.byref(ctx)) == 1
+    assert lib.alch_nb_create(ctypes.byref(p), arr, 1, None) == 1
+
+
+def test_empty_and_ragged_boxes_plan(lib):
+    """Boxes with zero atoms and very different sizes are accepted."""
+    from paper_2608_12691_amd import alchnb
+    p, keep = _params(alchnb, FF, skin=1.0)
+    s0, k0 = _system(alchnb, 0, 25.0, types=[], sol=[])
+    s1, k1 = _system(alchnb, 5, 25.0)
+    s2, k2 = _system(alchnb, 3, 40.0)
+    st, ctx = _create(lib, p, [s0, s1, s2])
+    assert st == 0
+    lib.alch_nb_destroy(ctx)
+
+
+def test_strerror_and_misc(lib):
+    for code in range(8):
+        assert lib.alch_nb_strerror(code)
+    assert lib.alch_nb_num_variants() >= 4
+    assert lib.alch_nb_flops_per_pair(0) > 50
+    assert lib.alch_nb_flops_per_pair(1) > lib.alch_nb_flops_per_pair(0)
+    offs = (ctypes.c_int32 * 16)()
+    assert lib.alch_nb_opes_layout(offs, 16) == 0
+    assert offs[15] + 101 == 16 + 4 * 101
+    assert lib.alch_nb_opes_layout(offs, 3) == 1

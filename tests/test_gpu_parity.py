@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2608_12691_amd import systems as S
+
+from conftest import workload
+from parity import TOL, compare, oracle_for, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _ctx(w, precision, schedule=O.BEUTLER, **kw):
+    from paper_2608_12691_amd import alchnb
+    return alchnb.from_workload(w, precision=precision, schedule=schedule, **kw)
+
+
+def _offsets(w):
+    return np.concatenate([[0], np.cumsum([s.n_atoms for s in w.systems])])
+
+
+def _run(ctx, w, lam, positions=None, flags=1):
+    pos_list = [s.positions for s in w.systems] if positions is None else positions
+    pos = ctx.positions(np.concatenate(pos_list))
+    res = ctx.compute_checked(pos, ctx.lambdas(lam), flags=flags)
+    torch.cuda.synchronize()
+    return to_numpy(res), pos_list
+
+
+@pytest.mark.parametrize("precision", [1, 0], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("schedule", [O.BEUTLER, O.LBF], ids=["beutler", "lbf"])
+def test_config1_parity(precision, schedule):
+    w = workload(1)
+    ctx = _ctx(w, precision, schedule)
+    for lam in (0.5, 0.0, 0.3, 0.75, 1.0):
+        print("config1 precision=%d schedule=%d lambda=%.2f" % (precision, schedule, lam), flush=True)
+        res, pos = _run(ctx, w, [lam])
+        assert res["flags"] == 0
+        ref = oracle_for(w, 0, lam, schedule)
+        compare(res, [ref], w, pos, precision, _offsets(w), label="cfg1 lam=%g" % lam)
+
+
+def test_config1_pair_set_bit_exact():
+    w = workload(1)
+    ctx = _ctx(w, 0)
+    pos = ctx.positions(w.systems)
+    ctx.build_list(pos)
+    got = ctx.export_pairs()
+    s = w.systems[0]
+    ref = O.pair_set(s.positions, s.exclusions, s.box, w.cutoff + w.skin)
+    assert got.shape == ref.shape
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+def test_deterministic_repeats(precision):
+    w = workload(1)
+    ctx = _ctx(w, precision)
+    pos = ctx.positions(w.systems)
+    lam = ctx.lambdas([0.62])
+    outs = []
+    for _ in range(5):
+        o = ctx.compute(pos, lam, flags=2)
+        torch.cuda.synchronize()
+        outs.append(to_numpy(o))
+    for o in outs[1:]:
+        for k in ("forces", "terms", "dudl", "n_pairs"):
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
+def test_ragged_batch_with_empty_box():
+    """Three boxes of different sizes, one of them empty, at different lambdas."""
+    rng = np.random.Generator(np.random.PCG64(99))
+    w1 = workload(1)
+    boxes = []
+    for n, L in ((0, 22.0), (150, 22.0), (400, 27.0)):
+        if n == 0:
+            boxes.append(S.System(positions=np.zeros((0, 3)), types=np.zeros(0, np.int32),
+                                  is_solute=np.zeros(0, np.uint8), exclusions=np.zeros((0, 2), np.int32),
+                                  box=np.full(3, L), molecule=np.zeros(0, np.int32)))
+        else:
+            boxes.append(S.random_tiny_system(rng, n, L, n_solute=6, n_types=w1.ff.n_types, min_dist=2.0))
+    w = S.Workload(name="ragged", systems=boxes, ff=w1.ff, cutoff=9.0, skin=1.0, switch_width=1.0, dsf_alpha=0.2,
+                   sc_alpha=0.5, lambdas=np.array([0.2, 0.45, 0.9]), seed=99)
+    for precision in (1, 0):
+        ctx = _ctx(w, precision)
+        res, pos = _run(ctx, w, w.lambdas)
+        refs = [oracle_for(w, k, w.lambdas[k], O.BEUTLER) if s.n_atoms else
+                dict(terms=np.zeros(10), forces=np.zeros((0, 3)), n_pairs=0, abs_terms=np.zeros(10))
+                for k, s in enumerate(w.systems)]
+        compare(res, refs, w, pos, precision, _offsets(w), label="ragged p%d" % precision)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+def test_config2_protocol(precision):
+    """24-atom solute in 3,000 waters, skin 1 A: a random walk with rebuilds."""
+    w = workload(2)
+    s = w.systems[0]
+    ctx = _ctx(w, precision)
+    walk = S.perturbation_walk(s, 121, 0.01, seed=7)
+    lams = S.lambda_draws(121, seed=8)
+    pos = ctx.positions(walk[0])
+    lam = ctx.lambdas([lams[0]])
+    out = ctx.new_outputs()
+    for t in range(121):
+        pos.copy_(torch.as_tensor(walk[t], device=pos.device))
+        lam.fill_(float(lams[t]))
+        ctx.compute(pos, lam, flags=1, out=out)
+        if t in (0, 60, 120):
+            torch.cuda.synchronize()
+            res = to_numpy(out)
+            ref = oracle_for(w, 0, lams[t], O.BEUTLER, positions=walk[t])
+            print("config2 call %d lambda %.3f" % (t, lams[t]), flush=True)
+            compare(res, [ref], w, [walk[t]], precision, _offsets(w), label="cfg2 t=%d" % t)
+    st = ctx.get_stats()
+    assert st["n_rebuilds"] >= 2  # the walk crosses skin/2 within ~100 calls
+    assert ctx.get_flags() == 0
+
+
+def test_config2_pair_set_after_walk():
+    w = workload(2)
+    s = w.systems[0]
+    ctx = _ctx(w, 0)
+    walk = S.perturbation_walk(s, 40, 0.05, seed=3)
+    pos = ctx.positions(walk[-1])
+    ctx.build_list(pos)
+    got = ctx.export_pairs()
+    ref = O.pair_set(walk[-1], s.exclusions, s.box, w.cutoff + w.skin)
+    assert np.array_equal(got, ref)
+
+
+def test_flags_forced_from_host():
+    w = workload(1)
+    ctx = _ctx(w, 0)
+    pos = ctx.positions(w.systems)
+    ctx.compute(pos, ctx.lambdas([1.5]), flags=2)
+    assert ctx.get_flags() & 8  # lambda clamped
+    bad = pos.clone()
+    bad[3, 1] = float("nan")
+    ctx.compute(bad, ctx.lambdas([0.5]), flags=0)
+    assert ctx.get_flags() & 4  # non-finite position
+    # a skin violation without automatic rebuild (config 2 has skin 1 A)
+    w2 = workload(2)
+    c2 = _ctx(w2, 0)
+    p2 = c2.positions(w2.systems)
+    c2.compute(p2, c2.lambdas([0.5]), flags=2)
+    assert c2.get_flags() == 0
+    moved = p2.clone()
+    moved[10, 0] += 0.8
+    c2.compute(moved, c2.lambdas([0.5]), flags=0)
+    assert c2.get_flags() & 2
+
+
+def test_graph_replay_matches_eager():
+    w = workload(2)
+    s = w.systems[0]
+    ctx = _ctx(w, 0)
+    walk = S.perturbation_walk(s, 6, 0.05, seed=21)
+    pos = ctx.positions(walk[0])
+    lam = ctx.lambdas([0.4])
+    out = ctx.new_outputs()
+    ctx.compute(pos, lam, flags=1, out=out)  # builds the list before capture
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gctx = _ctx(w, 0)
+        gout = gctx.new_outputs()
+        gpos = gctx.positions(walk[0])
+        glam = gctx.lambdas([0.4])
+        gctx.compute(gpos, glam, flags=1, out=gout)
+        gctx.capture_step(gpos, glam, gout)
+    for t in range(1, 6):
+        x = torch.as_tensor(walk[t], device=pos.device)
+        with torch.cuda.stream(stream):
+            gpos.copy_(x)
+            glam.fill_(0.1 * t)
+            gctx.launch_step()
+        stream.synchronize()
+        pos.copy_(x)
+        lam.fill_(0.1 * t)
+        ctx.compute(pos, lam, flags=1, out=out)
+        torch.cuda.synchronize()
+        a, b = to_numpy(gout), to_numpy(out)
+        for k in ("forces", "terms", "dudl", "n_pairs"):
+            assert np.array_equal(a[k], b[k]), (t, k)
