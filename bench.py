@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the alchemical nonbonded hot path on one MI355X.
+
+Workload (the 3,000-water call protocol): a 24-atom solute in 2,983 waters
+(8,973 atoms, 44.85 A cube, 100 atoms/nm^3), cutoff 10 A, skin 1 A, DSF
+a = 0.2 1/A, Beutler soft core.  Each step is one call of the hot path:
+positions advance by N(0, 0.01 A) per coordinate (a cumulative walk, inputs
+pre-generated in HBM), lambda is drawn uniformly in [0, 1], the device
+decides whether to rebuild the list (max displacement > skin/2), and the
+kernels return energies, forces and dU/dlambda.
+
+Prints one JSON line: pair-evals/s of the FP32/fixed-point path (the
+headline), the FP64 path beside it, the tile kernel's roofline position and
+the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector FLOP/s (256 CUs x 256 FLOP/clk x 2.4 GHz)
+PEAK_HBM = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("tile_kernels.hip", "anb_internal.h", "erfc_coeffs.h"):
+        with open(os.path.join(ROOT, "paper_2608_12691_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name):
+    """HBM bytes per tile launch from a committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_path(ctx, traj, lams, W, K, torch, graph):
+    """Warm up W steps, time K steps; returns (elapsed_s, tile_ms_avg, out)."""
+    from paper_2608_12691_amd import alchnb
+    dev = traj.device
+    pos = traj[0].clone()
+    lam = lams[0:1].clone()
+    out = ctx.new_outputs()
+    ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
+    if graph:
+        ctx.capture_step(pos, lam, out)
+
+    def step(t):
+        pos.copy_(traj[t])
+        lam.copy_(lams[t:t + 1])
+        if graph:
+            ctx.launch_step()
+        else:
+            ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
+
+    for t in range(W):
+        step(t)
+    torch.cuda.synchronize(dev)
+    st0 = ctx.get_stats()
+    ctx.set_timing(not graph)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for t in range(W, W + K):
+        step(t)
+    torch.cuda.synchronize(dev)
+    t1 = time.perf_counter()
+    ctx.set_timing(False)
+    st1 = ctx.get_stats()
+    n_t = st1["tile_launches_timed"] - st0["tile_launches_timed"]
+    tile_ms = (st1["tile_ms_total"] - st0["tile_ms_total"]) / n_t if n_t else None
+    return t1 - t0, tile_ms, out, st1["n_rebuilds"] - st0["n_rebuilds"], pos, lam
+
+
+def count_pairs(ctx, traj, lams, W, K, torch):
+    """Untimed pass over the same K calls: sum of evaluated pairs."""
+    from paper_2608_12691_amd import alchnb
+    pos = traj[0].clone()
+    lam = lams[0:1].clone()
+    out = ctx.new_outputs(forces=False)
+    acc = torch.zeros(1, dtype=torch.int64, device=traj.device)
+    for t in range(W, W + K):
+        pos.copy_(traj[t])
+        lam.copy_(lams[t:t + 1])
+        ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
+        acc += out["n_pairs"]
+    torch.cuda.synchronize()
+    return int(acc.item())
+
+
+def cpu_baseline(w, traj_np, lams_np, W, sample_calls):
+    import oracle as O
+    s = w.systems[0]
+    P = O.Params.of(w)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    O.evaluate(traj_np[W], s.types, s.is_solute, s.exclusions, s.box, w.ff.sigma, w.ff.epsilon, w.ff.charge, P,
+               lams_np[W], n_threads=threads)  # load and warm up
+    n = 0
+    t0 = time.perf_counter()
+    for t in range(W, W + sample_calls):
+        r = O.evaluate(traj_np[t], s.types, s.is_solute, s.exclusions, s.box, w.ff.sigma, w.ff.epsilon,
+                       w.ff.charge, P, lams_np[t], n_threads=threads)
+        n += r["n_pairs"]
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="pair-evals/s", cores=threads, kind="oracle",
+                sample="%d consecutive calls of the same walk (calls %d-%d), full O(N^2) FP64 evaluation each, "
+                       "%.1f s" % (sample_calls, W, W + sample_calls - 1, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--mode", choices=["graph", "eager"], default="eager")
+    ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-calls", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2608_12691_amd import alchnb, systems
+    if not os.path.exists(alchnb.LIB_PATH):
+        from paper_2608_12691_amd import build
+        build.build()
+    W, K = args.warmup, args.steps
+    w = systems.make_config(2)
+    s = w.systems[0]
+    log("workload", w.name, "atoms", s.n_atoms, "box", s.box[0])
+    traj_np = systems.perturbation_walk(s, W + K, 0.01, seed=systems.config_seed(2) + 500)
+    lams_np = systems.lambda_draws(W + K, seed=systems.config_seed(2) + 501)
+    dev = torch.device("cuda:0")
+    # all work on one non-default stream (graph capture needs one)
+    torch.cuda.set_stream(torch.cuda.Stream(dev))
+    traj = torch.as_tensor(traj_np, dtype=torch.float64, device=dev)
+    lams = torch.as_tensor(lams_np, dtype=torch.float64, device=dev)
+
+    res = {}
+    for prec in ([alchnb.FP32_FIXED] if args.no_fp64 else [alchnb.FP32_FIXED, alchnb.FP64]):
+        ctx = alchnb.from_workload(w, precision=prec, variant=args.variant)
+        # size the list once (grows the capacity if the first build overflows)
+        p0 = traj[0].clone()
+        ctx.compute_checked(p0, lams[0:1].clone(), flags=alchnb.FORCE_REBUILD)
+        if args.autotune:
+            ctx.autotune(p0, lams[0:1].clone())
+        elapsed, tile_ms, out, rebuilds, pos_last, lam_last = run_path(ctx, traj, lams, W, K, torch,
+                                                                        args.mode == "graph")
+        n_pairs = count_pairs(ctx, traj, lams, W, K, torch)
+        flags = ctx.get_flags()
+        stats = ctx.get_stats()
+        # final call's outputs for cross-precision errors
+        ctx.compute(pos_last, lam_last, flags=alchnb.AUTO_REBUILD, out=out)
+        torch.cuda.synchronize()
+        res[prec] = dict(elapsed=elapsed, tile_ms=tile_ms, n_pairs=n_pairs, rebuilds=rebuilds, flags=flags,
+                         stats=stats, forces=out["forces"].cpu().numpy(), dudl=float(out["dudl"][0]),
+                         terms=out["terms"][0].cpu().numpy())
+        log("precision", prec, "elapsed %.4f s" % elapsed, "tile %.2f us" % (1e3 * tile_ms if tile_ms else -1),
+            "pairs/call %.0f" % (n_pairs / K), "rebuilds", rebuilds, "flags", flags)
+        ctx.close()
+
+    r32 = res[alchnb.FP32_FIXED]
+    value = r32["n_pairs"] / r32["elapsed"]
+    pairs_per_call = r32["n_pairs"] / K
+    fpp = alchnb.flops_per_pair(0)
+    roof = None
+    if r32["tile_ms"]:
+        achieved = fpp * pairs_per_call / (r32["tile_ms"] * 1e-3)
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32, "traffic": measured_traffic("tile_fp32_water3000_traffic.json"),
+                "kernel": "k_tile<float, Beutler, switch>", "avg_launch_us": r32["tile_ms"] * 1e3,
+                "flop_per_pair": fpp, "pairs_per_launch": pairs_per_call}
+    line = {
+        "metric": "soft-core nonbonded pair-evals/s incl. forces+dU/dlambda; FP32-fixed vs FP64 GPU",
+        "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": 1e3 * r32["elapsed"] / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "24-atom solute in 2,983 waters (8,973 atoms), 44.85 A box, cutoff 10 A, skin 1 A, "
+                               "1 call per step: N(0,0.01 A) walk, lambda~U[0,1], device-side rebuild",
+                   "atoms": int(s.n_atoms), "pairs_per_call": pairs_per_call, "mode": args.mode,
+                   "rebuilds_in_timed_region": r32["rebuilds"], "variant": r32["stats"]["variant"]},
+        "roofline": roof,
+    }
+    if alchnb.FP64 in res:
+        r64 = res[alchnb.FP64]
+        v64 = r64["n_pairs"] / r64["elapsed"]
+        F32, F64 = r32["forces"], r64["forces"]
+        line["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["elapsed"] / K,
+                        "tile_us": r64["tile_ms"] * 1e3 if r64["tile_ms"] else None}
+        line["fp32_over_fp64"] = value / v64
+        line["fp32_error_vs_fp64"] = {
+            "force_rms_rel": float(np.sqrt(((F32 - F64) ** 2).sum() / (F64 ** 2).sum())),
+            "dudl_rel": abs(r32["dudl"] - r64["dudl"]) / max(abs(r64["dudl"]), 1e-300),
+            "energy_rel": float(abs(r32["terms"][8] - r64["terms"][8]) / max(abs(r64["terms"][8]), 1e-300))}
+    line["device_flags"] = {"fp32": r32["flags"], "fp64": res.get(alchnb.FP64, {}).get("flags")}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, traj_np, lams_np, W, args.cpu_calls)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

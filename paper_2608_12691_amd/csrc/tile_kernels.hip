@@ -174,6 +174,16 @@ __device__ inline void add_fixed(unsigned long long* p, R v, double scale, unsig
 
 // ------------------------------------------------------------ tile kernel
 
+// Coordinate k of atom a relative to the origin of its super-cluster s, in
+// the periodic image the atom had when the list was built: the displacement
+// since the build (minimum image) plus the build-time wrapped offset.  This
+// stays consistent with the list's image shifts for any super-cluster extent.
+__device__ inline double local_coord(const Dev& d, const double* __restrict__ x, int a, int s, int k, double L) {
+  double m = x[3 * a + k] - d.x_build[3 * a + k];
+  m -= L * rint(m / L);
+  return m + (d.xw[3 * a + k] - d.sc_origin[3 * s + k]);
+}
+
 // Solute-solvent pair (rare: only entries of kind KIND_ALCH).  Its inputs
 // are taken from FP64 sources and rounded once: the displacement from the
 // FP64 positions (minimum image), and sigma_ij, 4 eps_ij, k_e q_i q_j and
@@ -211,14 +221,17 @@ __device__ inline void alch_pair(R dx, R dy, R dz, bool valid, const typename C4
     const R hA = lv_or_hA, hB = le_or_hB;
     const R vdw = pc.lj0 * pc.S;
     const R fvdw = pc.flj0 * pc.S - pc.lj0 * pc.rdS;
+    // u_cap of eq. 6 for x < 1, written as the same polynomial expanded about
+    // x = 1 (t = 1 - x), which avoids the cancellation of the monomial form
+    // near the join: u = t(24 + t(228 + t(1232 + t(-3516 + t(3019.2 - 868 t)))))
     const R xr = pc.r * rcp(sij);
-    const R x2 = xr * xr, x3 = x2 * xr, x4 = x2 * x2;
+    const R t = R(1) - xr;
     const R epsq = R(0.25) * e4;
-    const R poly = x4 * (xr * (R(-868) * xr + R(2188.8)) - R(1440)) + R(119.2);
-    const R dpoly = x3 * (xr * (R(-5208) * xr + R(10944)) - R(5760));
+    const R poly = t * (R(24) + t * (R(228) + t * (R(1232) + t * (R(-3516) + t * (R(3019.2) + t * R(-868))))));
+    const R dpoly_dt = R(24) + t * (R(456) + t * (R(3696) + t * (R(-14064) + t * (R(15096) + t * R(-5208)))));
     const bool cap = xr < R(1);
     const R uc = cap ? epsq * poly : pc.lj0;
-    const R fuc = cap ? -epsq * dpoly * xr : pc.flj0;
+    const R fuc = cap ? epsq * dpoly_dt * xr : pc.flj0;   // -r du/dr = x du/dt
     const R ubv = uc * pc.S;
     const R fub = fuc * pc.S - uc * pc.rdS;
     u = hA * (vdw + pc.el) + hB * ubv;
@@ -289,15 +302,16 @@ __global__ void __launch_bounds__(kBlk) k_tile(Dev d, Pot<R> P, int xcd, double 
       const int jsl = jc * kCl + jl;
       const unsigned long long* __restrict__ mrow = d.ent_mask + (size_t)e * kScCl;
       R fjx = R(0), fjy = R(0), fjz = R(0), eent = R(0);
+      // offset of the j-cluster's image from the i-super-cluster origin
+      const int code = (int)((info >> 16) & 31u);
+      const int sj = jc >> 3;
+      const double odx = d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
+      const double ody = d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
+      const double odz = d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
       if (kind != KIND_ALCH) {
-        const int code = (int)((info >> 16) & 31u);
-        const int sj = jc >> 3;
-        const R ox = (R)(d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - ox0);
-        const R oy = (R)(d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0);
-        const R oz = (R)(d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0);
         const P4 pj = pos[jsl];
         const P2 qj = se[jsl];
-        const R xj = pj.x + ox, yj = pj.y + oy, zj = pj.z + oz;
+        const R xj = pj.x + (R)odx, yj = pj.y + (R)ody, zj = pj.z + (R)odz;
 #pragma unroll
         for (int c = 0; c < kScCl; ++c) {
           if (!(imask & (1u << c))) continue;
@@ -321,19 +335,20 @@ __global__ void __launch_bounds__(kBlk) k_tile(Dev d, Pot<R> P, int xcd, double 
           fiz[c] -= fz;
         }
       } else {
+        // FP64 local coordinates from the input positions, in this entry's image
         const int aj = max(0, d.slot_atom[jsl]);
-        const double xj = xin[3 * aj], yj = xin[3 * aj + 1], zj = xin[3 * aj + 2];
+        const double xj = local_coord(d, xin, aj, sj, 0, L0) + odx;
+        const double yj = local_coord(d, xin, aj, sj, 1, L1) + ody;
+        const double zj = local_coord(d, xin, aj, sj, 2, L2) + odz;
         const int tj = d.atom_type[aj];
 #pragma unroll
         for (int c = 0; c < kScCl; ++c) {
           if (!(imask & (1u << c))) continue;
           const bool valid = (mrow[c] >> lane) & 1ull;
           const int ai = max(0, d.slot_atom[s * kSc + c * kCl + il]);
-          double ddx = xj - xin[3 * ai], ddy = yj - xin[3 * ai + 1], ddz = zj - xin[3 * ai + 2];
-          ddx -= L0 * rint(ddx / L0);
-          ddy -= L1 * rint(ddy / L1);
-          ddz -= L2 * rint(ddz / L2);
-          const R dx = (R)ddx, dy = (R)ddy, dz = (R)ddz;
+          const double xl = local_coord(d, xin, ai, s, 0, L0), yl = local_coord(d, xin, ai, s, 1, L1),
+                       zl = local_coord(d, xin, ai, s, 2, L2);
+          const R dx = (R)(xj - xl), dy = (R)(yj - yl), dz = (R)(zj - zl);
           const P4 tp = tpair[d.atom_type[ai] * T + tj];
           R u, fr, rinv2;
           bool inr;
@@ -519,10 +534,7 @@ __global__ void __launch_bounds__(kBlk) k_canon(Dev d, const double* __restrict_
     } else {
       const ReplicaInfo& rp = d.reps[d.grids[d.atom_grid[a]].replica];
       double q[3];
-      for (int k = 0; k < 3; ++k) {
-        double t = pos[3 * a + k] - d.sc_origin[3 * s + k];
-        q[k] = t - rp.box[k] * rint(t / rp.box[k]);
-      }
+      for (int k = 0; k < 3; ++k) q[k] = local_coord(d, pos, a, s, k, rp.box[k]);
       v.x = (R)q[0];
       v.y = (R)q[1];
       v.z = (R)q[2];
