@@ -193,7 +193,9 @@ def main():
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32, "traffic": measured_traffic("tile_fp32_water3000_traffic.json"),
                 "kernel": "k_tile<float, Beutler, switch>", "avg_launch_us": r32["tile_ms"] * 1e3,
-                "flop_per_pair": fpp, "pairs_per_launch": pairs_per_call}
+                "flop_per_pair": fpp, "pairs_per_launch": pairs_per_call,
+                "tiles_per_launch": r32["stats"]["n_tiles"],
+                "pair_slot_efficiency": pairs_per_call / (64.0 * r32["stats"]["n_tiles"]) if r32["stats"]["n_tiles"] else None}
     line = {
         "metric": "soft-core nonbonded pair-evals/s incl. forces+dU/dlambda; FP32-fixed vs FP64 GPU",
         "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": K, "warmup": W,

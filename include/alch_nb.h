@@ -78,7 +78,8 @@ enum {
   ALCH_NB_FLAG_SKIN_EXCEEDED = 2u,  /* an atom moved > skin/2 since the list was built (no auto rebuild) */
   ALCH_NB_FLAG_NONFINITE = 4u,      /* a position was NaN or infinite */
   ALCH_NB_FLAG_LAMBDA_RANGE = 8u,   /* a lambda outside [0,1] was clamped */
-  ALCH_NB_FLAG_CAPACITY = 16u       /* the list did not fit its capacity; results of that call are invalid */
+  ALCH_NB_FLAG_CAPACITY = 16u,      /* the list did not fit its capacity; results of that call are invalid */
+  ALCH_NB_FLAG_BARRIER_TIMEOUT = 32u /* a list-build phase waited too long for the others; results invalid */
 };
 
 /* energy-term slots of alch_nb_out.terms, per system */
@@ -147,6 +148,7 @@ typedef struct {
   int64_t n_superclusters, n_entries, n_units;   /* current list (valid after a sync) */
   int64_t entry_capacity, unit_capacity;
   int64_t n_rebuilds;                            /* list builds since bind */
+  int64_t n_tiles;                               /* 64-pair tiles of the current list */
   int32_t variant;                               /* variant in use */
   int32_t entries_per_unit, blocks;              /* launch shape of the tile kernel */
   double tile_ms_total;                          /* summed tile-kernel time of timed calls */

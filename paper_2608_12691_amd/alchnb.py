@@ -14,7 +14,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libalchnb.so")
+LIB_PATH = os.environ.get("ALCHNB_LIB") or os.path.join(_HERE, "libalchnb.so")
 
 BEUTLER_DSF, LBF_DSF = 0, 1
 FP32_FIXED, FP64 = 0, 1
@@ -70,7 +70,8 @@ class Grad_t(ctypes.Structure):
 class Stats_t(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int64), ("n_systems", ctypes.c_int64), ("n_superclusters", ctypes.c_int64),
                 ("n_entries", ctypes.c_int64), ("n_units", ctypes.c_int64), ("entry_capacity", ctypes.c_int64),
-                ("unit_capacity", ctypes.c_int64), ("n_rebuilds", ctypes.c_int64), ("variant", ctypes.c_int32),
+                ("unit_capacity", ctypes.c_int64), ("n_rebuilds", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
+                ("variant", ctypes.c_int32),
                 ("entries_per_unit", ctypes.c_int32), ("blocks", ctypes.c_int32), ("tile_ms_total", ctypes.c_double),
                 ("tile_launches_timed", ctypes.c_int64)]
 

@@ -67,6 +67,7 @@ struct alch_nb_ctx {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
+  int fused_blocks = 0;  // blocks of the fused list build (0 = per-phase kernels)
   Dev dev{};
   PotConsts pc{};
   int variant = 0;
@@ -153,6 +154,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->ctr = cv.take<int>(base, 16);
   d->flags = cv.take<unsigned int>(base, 1);
   d->rebuild = cv.take<int>(base, 1);
+  d->barrier = cv.take<unsigned int>(base, 2);
   d->pos32 = cv.take<float4>(base, SL);
   d->pos64 = cv.take<double4>(base, SL);
   d->ffix = cv.take<unsigned long long>(base, 3 * SL);
@@ -437,6 +439,17 @@ alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* st
   lay_out(ctx, ctx->ws, &ctx->dev);
   Dev& d = ctx->dev;
   hipStream_t st = ctx->stream;
+  // every index table starts valid (zero) so that no phase can read garbage
+  HIPCHK(hipMemsetAsync(ctx->ws, 0, ctx->ws_bytes, st));
+  {
+    int dev_id = 0, n_cu = 0;
+    HIPCHK(hipGetDevice(&dev_id));
+    HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id));
+    const int per_cu = list_fused_max_blocks();
+    const char* env = std::getenv("ALCHNB_LIST_KERNELS");
+    const bool split = env && std::strcmp(env, "split") == 0;
+    ctx->fused_blocks = (!split && per_cu >= 1 && n_cu > 0) ? n_cu * std::min(per_cu, 2) : 0;
+  }
   auto up = [&](const void* dst, const void* src, size_t n) -> hipError_t {
     if (n == 0) return hipSuccess;
     return hipMemcpyAsync(const_cast<void*>(dst), src, n, hipMemcpyHostToDevice, st);
@@ -487,7 +500,7 @@ static alch_nb_status enqueue_compute(alch_nb_ctx* ctx, const double* pos, const
   const Dev& d = ctx->dev;
   hipStream_t st = ctx->stream;
   HIPCHK(launch_prepare(d, st, pos, lam, mode, 0.5 * p.skin, p.schedule));
-  HIPCHK(launch_list_build(d, st, pos, ctx->r_list, sh.epu));
+  HIPCHK(launch_list_build(d, st, pos, ctx->r_list, sh.epu, ctx->fused_blocks));
   HIPCHK(launch_canon(d, st, pos, p.precision));
   const bool timed = allow_timing && ctx->timing && ctx->n_timed < kTimingSlots;
   if (timed) HIPCHK(hipEventRecord(ctx->ev[2 * ctx->n_timed], st));
@@ -515,7 +528,7 @@ alch_nb_status alch_nb_build_list(alch_nb_ctx* ctx, const double* d_pos) {
   if (!d_pos) return ALCH_NB_E_INVALID_ARG;
   const Dev& d = ctx->dev;
   HIPCHK(launch_prepare(d, ctx->stream, d_pos, nullptr, 2, 0.5 * ctx->p.skin, ctx->p.schedule));
-  HIPCHK(launch_list_build(d, ctx->stream, d_pos, ctx->r_list, shape_of(ctx).epu));
+  HIPCHK(launch_list_build(d, ctx->stream, d_pos, ctx->r_list, shape_of(ctx).epu, ctx->fused_blocks));
   return ALCH_NB_OK;
 }
 
@@ -577,6 +590,7 @@ alch_nb_status alch_nb_get_stats(alch_nb_ctx* ctx, alch_nb_stats* s) {
   s->n_entries = c[CTR_ENT_NEED];
   s->n_units = c[CTR_UNIT_NEED];
   s->n_rebuilds = c[CTR_NBUILD];
+  s->n_tiles = c[CTR_TILES];
   s->n_superclusters = ctx->sc_cap;
   s->tile_ms_total = ctx->tile_ms;
   s->tile_launches_timed = ctx->tile_launches;

@@ -108,6 +108,7 @@ struct Dev {
   int* ctr;                  // [16] counters, see CTR_*
   unsigned int* flags;       // [1] sticky flags
   int* rebuild;              // [1]
+  unsigned int* barrier;     // [2] grid-barrier arrival count and generation
   // per call
   float4* pos32;             // [SC*64] local x, y, z, q
   double4* pos64;            // [SC*64]
@@ -119,7 +120,7 @@ struct Dev {
   const double4* tp64;       // [T*T]
 };
 
-enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5 };
+enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6 };
 
 constexpr int kPgBlocks = 512;  // blocks of the parameter-gradient pass
 

@@ -19,7 +19,12 @@ struct TileShape {
   int xcd;      // 1 = XCD-aware unit mapping
 };
 
-hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, double r_list, int epu);
+// fused_blocks > 0: one launch of the fused build with that many blocks
+// (all resident at once); 0: one launch per phase.
+hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, double r_list, int epu,
+                             int fused_blocks);
+// Resident blocks per compute unit of the fused list kernel (0 on error).
+int list_fused_max_blocks();
 hipError_t launch_units(const Dev& d, hipStream_t st, int epu);
 hipError_t launch_export(const Dev& d, hipStream_t st, double r_list, int* out, long long cap,
                          unsigned long long* counter);

@@ -27,7 +27,7 @@ __device__ inline double wrap_canon(double x, double L) { return __dsub_rn(x, __
 
 __device__ inline int gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ inline int gthreads() { return gridDim.x * blockDim.x; }
-__device__ inline int gwave() { return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); }
+__device__ inline int gwave() { return blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 __device__ inline int gwaves() { return gridDim.x * (blockDim.x >> 6); }
 
 // ------------------------------------------------------------ block scans
@@ -72,6 +72,7 @@ __device__ int block_scan_array(const int* src, int* dst, int n) {
 // ------------------------------------------------------------ phases
 
 __device__ void ph_begin(const Dev& d) {
+  if (gtid() == 0) d.ctr[CTR_TILES] = 0;
   for (int c = gtid(); c < d.n_cols; c += gthreads()) {
     d.col_count[c] = 0;
     d.col_fill[c] = 0;
@@ -451,25 +452,50 @@ __device__ inline bool is_excluded(const Dev& d, int a, int b) {
   return false;
 }
 
-// Atom-pair masks of each entry; lane = jl * 8 + il (the tile kernel's layout).
-__device__ void ph_masks(const Dev& d) {
+// Atom-pair masks of each entry; lane = jl * 8 + il (the tile kernel's
+// layout).  A bit is set for a valid, non-excluded pair (i<j inside one
+// cluster) whose build-time distance in this entry's image is below the list
+// radius; i-clusters left without any pair are dropped from the entry.
+__device__ void ph_masks(const Dev& d, double rl2) {
   const int lane = threadIdx.x & 63;
   const int il = lane & 7, jl = lane >> 3;
   const int n_ent = d.ctr[CTR_NENT];
   for (int e = gwave(); e < n_ent; e += gwaves()) {
     const int s = d.ent_isc[e];
     const int jc = d.ent_jc[e];
-    const uint32_t imask = d.ent_info[e] & 0xffu;
+    const uint32_t info = d.ent_info[e];
+    uint32_t imask = info & 0xffu;
+    const int code = (int)((info >> 16) & 31u);
     const int aj = d.slot_atom[jc * kCl + jl];
+    double sh[3] = {0, 0, 0};
+    if (aj >= 0) {
+      const ReplicaInfo& rp = d.reps[d.grids[d.atom_grid[aj]].replica];
+      sh[0] = (code % 3 - 1) * rp.box[0];
+      sh[1] = ((code / 3) % 3 - 1) * rp.box[1];
+      sh[2] = (code / 9 - 1) * rp.box[2];
+    }
+    uint32_t keep = 0;
     for (int c = 0; c < kScCl; ++c) {
       bool ok = false;
       if (imask & (1u << c)) {
         const int icl = s * kScCl + c;
         const int ai = d.slot_atom[icl * kCl + il];
-        ok = ai >= 0 && aj >= 0 && (icl != jc || il < jl) && !is_excluded(d, ai, aj);
+        if (ai >= 0 && aj >= 0 && (icl != jc || il < jl)) {
+          double r2 = 0;
+          for (int k = 0; k < 3; ++k) {
+            const double v = d.xw[3 * aj + k] + sh[k] - d.xw[3 * ai + k];
+            r2 += v * v;
+          }
+          ok = r2 < rl2 && !is_excluded(d, ai, aj);
+        }
       }
       const unsigned long long M = __ballot(ok);
+      if (M) keep |= 1u << c;
       if (lane == 0) d.ent_mask[(size_t)e * kScCl + c] = M;
+    }
+    if (lane == 0) {
+      if (keep != imask) d.ent_info[e] = (info & ~0xffu) | keep;
+      atomicAdd(&d.ctr[CTR_TILES], __popc(keep));  // 64-lane pair tiles of this list
     }
   }
 }
@@ -497,20 +523,88 @@ __global__ void __launch_bounds__(kBlk) k_units(Dev d, int epu, int force) {
   if (!force) { GATED; }
   ph_units(d, epu);
 }
-__global__ void __launch_bounds__(kBlk) k_masks(Dev d) { GATED; ph_masks(d); }
+__global__ void __launch_bounds__(kBlk) k_masks(Dev d, double rl2) { GATED; ph_masks(d, rl2); }
 __global__ void __launch_bounds__(kBlk) k_end(Dev d) { GATED; ph_end(d); }
 #undef GATED
 
 static inline int clampi(long long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); }
 
-hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, double r_list, int epu) {
+// Grid barrier for the fused list build.  Blocks arrive on a counter and
+// wait for a generation change; the wait is bounded, and a block that gives
+// up raises ALCH_NB_FLAG_BARRIER_TIMEOUT and proceeds, so every wave always
+// finishes.  The grid is sized on the host to fit the device at once.
+__device__ inline void grid_barrier(const Dev& d, unsigned int& gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    unsigned int* bar = d.barrier;
+    const unsigned int g = gen;
+    if (atomicAdd(&bar[0], 1u) == gridDim.x - 1) {
+      atomicExch(&bar[0], 0u);
+      __threadfence();
+      atomicAdd(&bar[1], 1u);
+    } else {
+      unsigned int spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(8);
+        if (++spins > (1u << 22)) {
+          atomicOr(d.flags, 32u);
+          break;
+        }
+      }
+    }
+    __threadfence();
+    gen = g + 1;
+  }
+  __syncthreads();
+}
+
+// The whole list build in one launch (phases separated by grid barriers).
+__global__ void __launch_bounds__(kBlk) k_list_fused(Dev d, const double* __restrict__ pos, double rlm, double rl2,
+                                                     int epu) {
+  if (!rebuild_on(d)) return;
+  __shared__ unsigned int gen_s;
+  if (threadIdx.x == 0) gen_s = __hip_atomic_load(&d.barrier[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  unsigned int gen = gen_s;
+  ph_begin(d);
+  grid_barrier(d, gen);
+  ph_bin(d, pos);
+  grid_barrier(d, gen);
+  ph_scan_cols(d);
+  grid_barrier(d, gen);
+  ph_scatter(d);
+  grid_barrier(d, gen);
+  ph_sort_cols(d);
+  grid_barrier(d, gen);
+  ph_build_sc(d);
+  grid_barrier(d, gen);
+  ph_search<false>(d, rlm);
+  grid_barrier(d, gen);
+  ph_scan_entries(d);
+  grid_barrier(d, gen);
+  ph_search<true>(d, rlm);
+  grid_barrier(d, gen);
+  ph_units(d, epu);
+  ph_masks(d, rl2);
+  grid_barrier(d, gen);
+  ph_end(d);
+}
+
+hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, double r_list, int epu,
+                             int fused_blocks) {
   const double rlm = r_list * (1.0 + 1e-12) + 1e-9;  // conservative box test
+  const double rl2 = rlm * rlm;  // masks keep the same margin; the export test is exact
   const dim3 B(kBlk);
-  const int g_atoms = clampi((d.n_atoms + kBlk - 1) / kBlk, 1, 2048);
-  const int g_cols = clampi(d.n_cols, 1, 2048);
-  const int g_sc = clampi((d.sc_cap + 3) / 4, 1, 4096);
-  const int g_ent = clampi(((long long)d.ent_cap + 3) / 4, 1, 4096);
-  hipLaunchKernelGGL(k_begin, dim3(clampi((d.n_cols + kBlk - 1) / kBlk, 1, 256)), B, 0, st, d);
+  if (fused_blocks > 0) {
+    hipLaunchKernelGGL(k_list_fused, dim3(fused_blocks), B, 0, st, d, pos, rlm, rl2, epu);
+    return hipGetLastError();
+  }
+  const int g_atoms = clampi((d.n_atoms + kBlk - 1) / kBlk, 1, 512);
+  const int g_cols = clampi(d.n_cols, 1, 512);
+  const int g_sc = clampi((d.sc_cap + 3) / 4, 1, 512);
+  const int g_ent = clampi(((long long)d.ent_cap + 3) / 4, 1, 512);
+  hipLaunchKernelGGL(k_begin, dim3(clampi((d.n_cols + kBlk - 1) / kBlk, 1, 64)), B, 0, st, d);
   hipLaunchKernelGGL(k_bin, dim3(g_atoms), B, 0, st, d, pos);
   hipLaunchKernelGGL(k_scan_cols, dim3(1), B, 0, st, d);
   hipLaunchKernelGGL(k_scatter, dim3(g_atoms), B, 0, st, d);
@@ -520,9 +614,17 @@ hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, do
   hipLaunchKernelGGL(k_scan_entries, dim3(1), B, 0, st, d);
   hipLaunchKernelGGL(k_search_write, dim3(g_sc), B, 0, st, d, rlm);
   hipLaunchKernelGGL(k_units, dim3(1), B, 0, st, d, epu, 0);
-  hipLaunchKernelGGL(k_masks, dim3(g_ent), B, 0, st, d);
+  hipLaunchKernelGGL(k_masks, dim3(g_ent), B, 0, st, d, rl2);
   hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, st, d);
   return hipGetLastError();
+}
+
+int list_fused_max_blocks() {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_list_fused), kBlk, 0) !=
+      hipSuccess)
+    return 0;
+  return per_cu;
 }
 
 hipError_t launch_units(const Dev& d, hipStream_t st, int epu) {

@@ -161,6 +161,24 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Read-only view of list data inside the tile kernel: the constant address
+// space tells the compiler the memory is not written during the launch, so
+// wave-uniform reads become scalar loads.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ inline cptr<T> as_const(const T* p) {
+  return (cptr<T>)p;
+}
+
+// Orders this wave's LDS writes before other lanes of the same wave read
+// them (each wave owns its LDS slice, so no block-wide barrier is needed).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename R>
 __device__ inline void add_fixed(unsigned long long* p, R v, double scale, unsigned int* flags) {
   if (v == R(0)) return;
@@ -254,16 +272,35 @@ __global__ void __launch_bounds__(kBlk) k_tile(Dev d, Pot<R> P, int xcd, double 
   const int slots = d.sc_cap * kSc;
   const int T = d.n_types;
   const int lane = threadIdx.x & 63;
+  __shared__ P4 ipos_all[kBlk];
+  __shared__ P2 ise_all[kBlk];
+  P4* ipos = ipos_all + (threadIdx.x & ~63);
+  P2* ise = ise_all + (threadIdx.x & ~63);
   const int il = lane & 7, jl = lane >> 3;
   const int n_units = d.ctr[CTR_NUNIT];
-  int b = blockIdx.x;
-  if (xcd && (gridDim.x & 7) == 0) b = (b & 7) * (gridDim.x >> 3) + (b >> 3);
-  const int nw = gridDim.x * (kBlk / 64);
-  const int lw = b * (kBlk / 64) + (threadIdx.x >> 6);
-  const int per = (n_units + nw - 1) / nw;
-  const int ub = lw * per, ue = min(n_units, ub + per);
+  // Unit range of this wave.  XCD-aware: blocks are dispatched round-robin
+  // over the 8 XCDs, so XCD x (blocks b with b % 8 == x) takes the x-th
+  // contiguous eighth of the units (neighbouring super-clusters share
+  // j-clusters, which then stay in that XCD's L2) and splits it evenly
+  // over its waves.  Otherwise consecutive waves take consecutive runs.
+  // wave index made provably uniform: unit and entry indices then live in
+  // scalar registers and their loads are scalar loads
+  const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int ub, ue;
+  if (xcd && (gridDim.x & 7) == 0) {
+    const int x = blockIdx.x & 7, nbx = gridDim.x >> 3, lb = blockIdx.x >> 3;
+    const int c0 = (int)((long long)n_units * x / 8), c1 = (int)((long long)n_units * (x + 1) / 8);
+    const int nwx = nbx * (kBlk / 64), w = lb * (kBlk / 64) + wib;
+    ub = c0 + (int)((long long)(c1 - c0) * w / nwx);
+    ue = c0 + (int)((long long)(c1 - c0) * (w + 1) / nwx);
+  } else {
+    const int nw = gridDim.x * (kBlk / 64), w = blockIdx.x * (kBlk / 64) + wib;
+    ub = (int)((long long)n_units * w / nw);
+    ue = (int)((long long)n_units * (w + 1) / nw);
+  }
   for (int u = ub; u < ue; ++u) {
-    const int4 U = d.units[u];
+    const cptr<int> up = as_const(reinterpret_cast<const int*>(d.units)) + 4 * u;
+    const int4 U = make_int4(up[0], up[1], up[2], up[3]);
     const int s = U.x;
     const ReplicaInfo& rp = d.reps[U.w];
     const double L0 = rp.box[0], L1 = rp.box[1], L2 = rp.box[2];
@@ -276,52 +313,83 @@ __global__ void __launch_bounds__(kBlk) k_tile(Dev d, Pot<R> P, int xcd, double 
       la0 = (R)lam.a[0];
       la1 = (R)lam.a[1];
     }
-    R xi[kScCl], yi[kScCl], zi[kScCl], qi[kScCl], si[kScCl], ei[kScCl];
+    // the super-cluster's 64 atoms go to this wave's LDS slice (lane l holds
+    // slot l); lane (jl, il) then reads atom c*8 + il for each i-cluster c
     R fix[kScCl], fiy[kScCl], fiz[kScCl];
+    wave_sync();
+    ipos[lane] = pos[s * kSc + lane];
+    ise[lane] = se[s * kSc + lane];
+    wave_sync();
 #pragma unroll
-    for (int c = 0; c < kScCl; ++c) {
-      const int sl = s * kSc + c * kCl + il;
-      const P4 p = pos[sl];
-      const P2 q = se[sl];
-      xi[c] = p.x;
-      yi[c] = p.y;
-      zi[c] = p.z;
-      qi[c] = p.w;
-      si[c] = q.x;
-      ei[c] = q.y;
-      fix[c] = fiy[c] = fiz[c] = R(0);
-    }
-    const double ox0 = d.sc_origin[3 * s], oy0 = d.sc_origin[3 * s + 1], oz0 = d.sc_origin[3 * s + 2];
+    for (int c = 0; c < kScCl; ++c) fix[c] = fiy[c] = fiz[c] = R(0);
+    const double ox0 = as_const(d.sc_origin)[3 * s], oy0 = as_const(d.sc_origin)[3 * s + 1],
+                 oz0 = as_const(d.sc_origin)[3 * s + 2];
     double acc_solv = 0, acc_solu = 0, acc_a0 = 0, acc_a1 = 0, acc_a2 = 0;
     int npair = 0;
+    // software pipeline: entry words two ahead, j-cluster data one ahead
+    const cptr<int> ejc = as_const(d.ent_jc);
+    const cptr<uint32_t> einfo = as_const(d.ent_info);
+    const cptr<double> sorg = as_const(d.sc_origin);
+    int jc_a = ejc[U.y];
+    uint32_t info_a = einfo[U.y];
+    int jc_b = jc_a;
+    uint32_t info_b = info_a;
+    if (U.y + 1 < U.z) {
+      jc_b = ejc[U.y + 1];
+      info_b = einfo[U.y + 1];
+    }
+    P4 pj_a = pos[jc_a * kCl + jl];
+    P2 qj_a = se[jc_a * kCl + jl];
+    const cptr<unsigned long long> emask = as_const(d.ent_mask);
+    unsigned long long m_a[kScCl];
+#pragma unroll
+    for (int c = 0; c < kScCl; ++c) m_a[c] = emask[(size_t)U.y * kScCl + c];
     for (int e = U.y; e < U.z; ++e) {
-      const int jc = d.ent_jc[e];
-      const uint32_t info = d.ent_info[e];
+      unsigned long long mcur[kScCl];
+#pragma unroll
+      for (int c = 0; c < kScCl; ++c) mcur[c] = m_a[c];
+      if (e + 1 < U.z) {
+#pragma unroll
+        for (int c = 0; c < kScCl; ++c) m_a[c] = emask[(size_t)(e + 1) * kScCl + c];
+      }
+      const int jc = jc_a;
+      const uint32_t info = info_a;
+      const P4 pj = pj_a;
+      const P2 qj = qj_a;
+      jc_a = jc_b;
+      info_a = info_b;
+      if (e + 1 < U.z) {
+        pj_a = pos[jc_a * kCl + jl];
+        qj_a = se[jc_a * kCl + jl];
+      }
+      if (e + 2 < U.z) {
+        jc_b = ejc[e + 2];
+        info_b = einfo[e + 2];
+      }
       const uint32_t imask = info & 0xffu;
       const int kind = (int)((info >> 8) & 3u);
       const int jsl = jc * kCl + jl;
-      const unsigned long long* __restrict__ mrow = d.ent_mask + (size_t)e * kScCl;
       R fjx = R(0), fjy = R(0), fjz = R(0), eent = R(0);
       // offset of the j-cluster's image from the i-super-cluster origin
       const int code = (int)((info >> 16) & 31u);
       const int sj = jc >> 3;
-      const double odx = d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
-      const double ody = d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
-      const double odz = d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
+      const double odx = sorg[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
+      const double ody = sorg[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
+      const double odz = sorg[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
       if (kind != KIND_ALCH) {
-        const P4 pj = pos[jsl];
-        const P2 qj = se[jsl];
         const R xj = pj.x + (R)odx, yj = pj.y + (R)ody, zj = pj.z + (R)odz;
 #pragma unroll
         for (int c = 0; c < kScCl; ++c) {
           if (!(imask & (1u << c))) continue;
-          const bool valid = (mrow[c] >> lane) & 1ull;
-          const R dx = xj - xi[c], dy = yj - yi[c], dz = zj - zi[c];
+          const bool valid = (mcur[c] >> lane) & 1ull;
+          const P4 pi = ipos[c * kCl + il];
+          const P2 qi = ise[c * kCl + il];
+          const R dx = xj - pi.x, dy = yj - pi.y, dz = zj - pi.z;
           const R r2 = dx * dx + dy * dy + dz * dz;
           const bool inr = valid && r2 < P.rc2;
           npair += __popcll(__ballot(inr));
           PairCore<R, SW> pc;
-          pc.eval(r2, inr, si[c] + qj.x, ei[c] * qj.y, qi[c] * pj.w, P);
+          pc.eval(r2, inr, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P);
           const R u = pc.lj0 * pc.S + pc.el;
           const R fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
           const R fs = inr ? fr * pc.rinv2 : R(0);
@@ -344,7 +412,7 @@ __global__ void __launch_bounds__(kBlk) k_tile(Dev d, Pot<R> P, int xcd, double 
 #pragma unroll
         for (int c = 0; c < kScCl; ++c) {
           if (!(imask & (1u << c))) continue;
-          const bool valid = (mrow[c] >> lane) & 1ull;
+          const bool valid = (mcur[c] >> lane) & 1ull;
           const int ai = max(0, d.slot_atom[s * kSc + c * kCl + il]);
           const double xl = local_coord(d, xin, ai, s, 0, L0), yl = local_coord(d, xin, ai, s, 1, L1),
                        zl = local_coord(d, xin, ai, s, 2, L2);
@@ -481,7 +549,10 @@ __global__ void __launch_bounds__(kBlk) k_prepare(Dev d, const double* __restric
     for (int k = 0; k < 4; ++k) s.f[k] = (float)s.a[k];
     d.lam[t] = s;
   }
-  if (t == 0 && mode == 2) __atomic_store_n(d.rebuild, 1, __ATOMIC_RELAXED);
+  if (t == 0) {
+    if (mode == 2) __atomic_store_n(d.rebuild, 1, __ATOMIC_RELAXED);
+    d.barrier[0] = 0u;  // arrival counter of the list build's grid barrier (clean after any timeout)
+  }
   const bool have_list = d.ctr[CTR_NBUILD] > 0;
   bool moved = false, bad = false;
   for (int a = t; a < d.n_atoms; a += gthreads()) {
