@@ -79,7 +79,8 @@ enum {
   ALCH_NB_FLAG_NONFINITE = 4u,      /* a position was NaN or infinite */
   ALCH_NB_FLAG_LAMBDA_RANGE = 8u,   /* a lambda outside [0,1] was clamped */
   ALCH_NB_FLAG_CAPACITY = 16u,      /* the list did not fit its capacity; results of that call are invalid */
-  ALCH_NB_FLAG_BARRIER_TIMEOUT = 32u /* a list-build phase waited too long for the others; results invalid */
+  ALCH_NB_FLAG_BARRIER_TIMEOUT = 32u,/* a list-build phase waited too long for the others; results invalid */
+  ALCH_NB_FLAG_BAD_INDEX = 64u       /* alch_nb_dihedrals met an atom index outside [0, N); that CV was skipped */
 };
 
 /* energy-term slots of alch_nb_out.terms, per system */
@@ -183,8 +184,10 @@ alch_nb_status alch_nb_compute(alch_nb_ctx *ctx, const double *d_pos, const doub
 alch_nb_status alch_nb_backward(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda,
                                 const double *d_grad_energy, const alch_nb_grad *grad);
 
-/* Dihedral collective variables xi_c (atom quadruples d_idx [n_cv][4],
- * global indices) with their Cartesian gradients d_dxi [n_cv][4][3], and,
+/* Dihedral collective variables xi_c in (-pi, pi] (atom quadruples d_idx
+ * [n_cv][4], global indices; bond vectors by minimum image in the box of
+ * the second atom; an index outside [0, N) skips that CV and raises
+ * ALCH_NB_FLAG_BAD_INDEX) with their Cartesian gradients d_dxi [n_cv][4][3], and,
  * when d_mass_inv [N_total] is given, the sum_i m_i^-1 |dxi/dr_i|^2 of the
  * paper's eq. 16 into d_msum [n_cv].  With d_s and d_kappa [n_cv] the
  * d-AFED coupling (eq. 15) energy goes to d_u_dafed [1] and its force is
@@ -194,17 +197,31 @@ alch_nb_status alch_nb_dihedrals(alch_nb_ctx *ctx, const double *d_pos, int32_t 
                                  double *d_xi, double *d_dxi, const double *d_mass_inv, double *d_msum,
                                  const double *d_s, const double *d_kappa, double *d_u_dafed, double *d_forces);
 
-/* Lambda/OPES state update for one box (the paper's mirror-periodic theta,
- * eq. 3, and the dual OPES bias, eqs. 11-14, on a periodic theta grid).
- * d_state is a device array of ALCH_NB_OPES_STATE doubles laid out as
- * described at alch_nb_opes_layout(); d_dudl [1] is dU/dlambda from the
- * last compute.  Writes lambda to d_lambda_out [1], the bias to d_state.
- * deposit != 0 adds a kernel at the current theta to both biases. */
+/* Lambda/OPES for one box: the paper's mirror-periodic theta (eq. 3) and
+ * the dual OPES bias U = U_Standard + U_Explore (eqs. 11-14) on theta, with
+ * uncompressed Gaussian kernels of width sigma on the periodic [0, 2) line.
+ * The state is one device array of alch_nb_opes_state_size(capacity)
+ * doubles (layout from alch_nb_opes_layout(): header slots theta, lambda,
+ * dlambda/dtheta, U_OPES, dU_OPES/dtheta, F_theta, kT, sigma, the two
+ * barriers, kernel count, capacity and running sums; then the bias and its
+ * derivative on 101 output grid nodes theta_g = 2g/101; then the kernel
+ * centres and their Standard weights).  The caller may write theta (slot 0)
+ * between calls, e.g. from an integrator.
+ * alch_nb_opes_init: zeroes the state and sets the constants (kcal/mol).
+ * alch_nb_opes_update: optionally deposits a kernel at the current theta
+ * (Standard weight exp(U_total/kT), Explore weight 1; no deposit once the
+ * capacity is reached), then writes lambda (eq. 3) to d_lambda_out [1], the
+ * bias and F_theta = -(dlambda/dtheta) dU/dlambda - dU_OPES/dtheta with
+ * dU/dlambda read from d_dudl [1] (NULL = 0).  The grid is refreshed on
+ * deposition.  Device pointers; FP64; one thread block. */
 #define ALCH_NB_OPES_GRID 101
-#define ALCH_NB_OPES_STATE (16 + 4 * ALCH_NB_OPES_GRID)
+#define ALCH_NB_OPES_HEADER 16
+int64_t alch_nb_opes_state_size(int32_t capacity);
+alch_nb_status alch_nb_opes_init(alch_nb_ctx *ctx, double *d_state, int32_t capacity, double kT, double sigma,
+                                 double barrier_std, double barrier_expl, double theta0);
 alch_nb_status alch_nb_opes_update(alch_nb_ctx *ctx, double *d_state, const double *d_dudl, double *d_lambda_out,
                                    int32_t deposit);
-/* Offsets inside the OPES state array (host query, no HIP call). */
+/* Offsets of the state sections (host query, no HIP call); n >= 18. */
 alch_nb_status alch_nb_opes_layout(int32_t *offsets, int32_t n);
 
 /* Write the current list's pair set (i<j global indices, canonical FP64

@@ -20,17 +20,18 @@ BEUTLER_DSF, LBF_DSF = 0, 1
 FP32_FIXED, FP64 = 0, 1
 AUTO_REBUILD, FORCE_REBUILD = 1, 2
 FLAG_FIXED_OVERFLOW, FLAG_SKIN_EXCEEDED, FLAG_NONFINITE, FLAG_LAMBDA_RANGE, FLAG_CAPACITY = 1, 2, 4, 8, 16
+FLAG_BARRIER_TIMEOUT, FLAG_BAD_INDEX = 32, 64
 NTERMS = 10
 TERM_NAMES = ["E_solv_solv", "E_solu_solu", "E_ss_vdw", "E_ss_elec", "U_A", "U_B", "dUdl_vdw", "dUdl_elec",
               "E_total", "dUdl_total"]
 OPES_GRID = 101
-OPES_STATE = 16 + 4 * OPES_GRID
+OPES_HEADER = 16
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "box too small", 3: "unsupported", 4: "capacity", 5: "hip error",
           6: "not bound", 7: "no device"}
 
 EXPORTED = ["alch_nb_create", "alch_nb_workspace_size", "alch_nb_bind", "alch_nb_build_list", "alch_nb_compute",
-            "alch_nb_backward", "alch_nb_dihedrals", "alch_nb_opes_update", "alch_nb_opes_layout",
+            "alch_nb_backward", "alch_nb_dihedrals", "alch_nb_opes_update", "alch_nb_opes_layout", "alch_nb_opes_init", "alch_nb_opes_state_size",
             "alch_nb_export_pairs", "alch_nb_capture_step", "alch_nb_launch_step", "alch_nb_autotune",
             "alch_nb_set_variant", "alch_nb_num_variants", "alch_nb_set_timing", "alch_nb_get_flags",
             "alch_nb_get_stats", "alch_nb_destroy", "alch_nb_strerror", "alch_nb_last_hip_error",
@@ -97,6 +98,8 @@ def load():
             "alch_nb_dihedrals": ([P, P, I32, P, P, P, P, P, P, P, P, P], I32),
             "alch_nb_opes_update": ([P, P, P, P, I32], I32),
             "alch_nb_opes_layout": ([P, I32], I32),
+            "alch_nb_opes_init": ([P, P, I32, D, D, D, D, D], I32),
+            "alch_nb_opes_state_size": ([I32], I64),
             "alch_nb_export_pairs": ([P, P, I64, P], I32),
             "alch_nb_capture_step": ([P, P, P, P], I32),
             "alch_nb_launch_step": ([P], I32),
@@ -165,6 +168,7 @@ class Context:
                            float(cutoff), float(skin), float(switch_width), float(dsf_alpha), float(sc_alpha),
                            self.schedule, self.precision, int(variant), float(capacity_factor))
         self.ctx = None
+        self.generation = 0  # forwards enqueued (the backward needs the state of its own forward)
         self._create()
         self.stream = torch.cuda.current_stream(self.device)
         self._bind()
@@ -245,6 +249,7 @@ class Context:
         assert pos.dtype == self.torch.float64 and pos.is_contiguous() and pos.shape == (self.N, 3)
         assert lam.dtype == self.torch.float64 and lam.is_contiguous() and lam.shape == (self.K,)
         out = out if out is not None else self.new_outputs()
+        self.generation += 1
         o = self._out_struct(out)
         self._out_keep = o
         st = self.lib.alch_nb_compute(self.ctx, ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
@@ -285,10 +290,21 @@ class Context:
         self._check("alch_nb_dihedrals", st)
         return dict(xi=xi, dxi=dxi, msum=msum, u_dafed=u)
 
+    def opes_state(self, capacity, kT, sigma=0.10, barrier_std=30.0, barrier_expl=5.0, theta0=0.0):
+        """New device OPES state (float64) initialised on the bound stream."""
+        n = int(self.lib.alch_nb_opes_state_size(int(capacity)))
+        if n <= 0:
+            raise AlchNBError("alch_nb_opes_state_size", 1)
+        st = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        self._check("alch_nb_opes_init", self.lib.alch_nb_opes_init(self.ctx, ctypes.c_void_p(st.data_ptr()),
+                                                                    int(capacity), float(kT), float(sigma),
+                                                                    float(barrier_std), float(barrier_expl),
+                                                                    float(theta0)))
+        return st
+
     def opes_update(self, state, dudl, lam_out, deposit=False):
-        st = self.lib.alch_nb_opes_update(self.ctx, ctypes.c_void_p(state.data_ptr()),
-                                          ctypes.c_void_p(dudl.data_ptr()), ctypes.c_void_p(lam_out.data_ptr()),
-                                          int(bool(deposit)))
+        st = self.lib.alch_nb_opes_update(self.ctx, ctypes.c_void_p(state.data_ptr()), _addr(dudl),
+                                          _addr(lam_out), int(bool(deposit)))
         self._check("alch_nb_opes_update", st)
 
     def export_pairs(self, cap=None):

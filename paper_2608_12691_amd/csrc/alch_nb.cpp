@@ -110,6 +110,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->n_types = ctx->T;
   d->atom_type = cv.take<int>(base, N);
   d->atom_grid = cv.take<int>(base, N);
+  d->atom_rep = cv.take<int>(base, N);
   d->grid_atoms = cv.take<int>(base, N);
   d->grids = cv.take<GridInfo>(base, ctx->G);
   d->reps = cv.take<ReplicaInfo>(base, K);
@@ -160,6 +161,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->ffix = cv.take<unsigned long long>(base, 3 * SL);
   d->unit_acc = cv.take<double>(base, U * NACC);
   d->lam = cv.take<LamState>(base, K);
+  d->last_dudl = cv.take<double>(base, K);
   d->pgrad_part = cv.take<double>(base, (size_t)kPgBlocks * 3 * ctx->T);
   d->tp32 = cv.take<float4>(base, (size_t)ctx->T * ctx->T);
   d->tp64 = cv.take<double4>(base, (size_t)ctx->T * ctx->T);
@@ -202,13 +204,9 @@ double alch_nb_flops_per_pair(int32_t kind) {
 }
 
 alch_nb_status alch_nb_opes_layout(int32_t* offsets, int32_t n) {
-  // 0: theta, 1: lambda, 2: dlambda/dtheta, 3: U_opes, 4: dU_opes/dtheta,
-  // 5: F_theta, 6: kT, 7: sigma, 8: barrier_std, 9: barrier_expl,
-  // 10: n_deposited, 11: sum of Standard weights, 12..15 reserved,
-  // 16: rho_std[GRID], 16+GRID: rho_expl[GRID], 16+2 GRID: bias[GRID],
-  // 16+3 GRID: dbias[GRID]
-  const int32_t v[] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 16, 16 + ALCH_NB_OPES_GRID, 16 + 2 * ALCH_NB_OPES_GRID,
-                       16 + 3 * ALCH_NB_OPES_GRID};
+  const int32_t v[] = {OPES_THETA, OPES_LAMBDA, OPES_DLAM, OPES_U, OPES_DU, OPES_FTHETA, OPES_KT, OPES_SIGMA,
+                       OPES_DE_STD, OPES_DE_EXPL, OPES_N, OPES_CAP, OPES_S_STD, OPES_S_EXPL, OPES_W_STD,
+                       OPES_HEADER, OPES_HEADER + OPES_GRID_N, OPES_HEADER + 2 * OPES_GRID_N};
   const int32_t m = (int32_t)(sizeof(v) / sizeof(v[0]));
   if (!offsets || n < m) return ALCH_NB_E_INVALID_ARG;
   for (int i = 0; i < m; ++i) offsets[i] = v[i];
@@ -456,6 +454,7 @@ alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* st
   };
   HIPCHK(up(d.atom_type, ctx->atom_type.data(), sizeof(int) * ctx->N));
   HIPCHK(up(d.atom_grid, ctx->atom_grid.data(), sizeof(int) * ctx->N));
+  HIPCHK(up(d.atom_rep, ctx->atom_rep.data(), sizeof(int) * ctx->N));
   HIPCHK(up(d.grid_atoms, ctx->grid_atoms.data(), sizeof(int) * ctx->grid_atoms.size()));
   HIPCHK(up(d.grids, ctx->grids.data(), sizeof(GridInfo) * ctx->G));
   HIPCHK(up(d.reps, ctx->reps.data(), sizeof(ReplicaInfo) * ctx->K));
@@ -647,17 +646,59 @@ void alch_nb_destroy(alch_nb_ctx* ctx) {
   delete ctx;
 }
 
-// ------------------------------------------------------------------ not yet
-alch_nb_status alch_nb_backward(alch_nb_ctx* ctx, const double*, const double*, const double*, const alch_nb_grad*) {
-  return ctx ? ALCH_NB_E_UNSUPPORTED : ALCH_NB_E_INVALID_ARG;
+alch_nb_status alch_nb_backward(alch_nb_ctx* ctx, const double* d_pos, const double* d_lambda,
+                                const double* d_grad_energy, const alch_nb_grad* grad) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!d_pos || !d_lambda || !d_grad_energy || !grad) return ALCH_NB_E_INVALID_ARG;
+  (void)d_lambda;  // the lambda factors of the last forward are kept on the device
+  const Dev& d = ctx->dev;
+  if (grad->d_pos || grad->d_lambda)
+    HIPCHK(launch_backward_finish(d, ctx->stream, ctx->p.precision, d_grad_energy, grad->d_pos, grad->d_lambda));
+  if (grad->d_sigma || grad->d_sqrt_epsilon || grad->d_charge) {
+    if (ctx->T > kMaxTypes) return ALCH_NB_E_UNSUPPORTED;
+    HIPCHK(launch_param_grads(d, ctx->stream, ctx->pc, ctx->p.precision, ctx->p.schedule, d_pos, d_grad_energy,
+                              grad->d_sigma, grad->d_sqrt_epsilon, grad->d_charge));
+  }
+  return ALCH_NB_OK;
 }
-alch_nb_status alch_nb_dihedrals(alch_nb_ctx* ctx, const double*, int32_t, const int32_t*, double*, double*,
-                                 const double*, double*, const double*, const double*, double*, double*) {
-  return ctx ? ALCH_NB_E_UNSUPPORTED : ALCH_NB_E_INVALID_ARG;
+
+alch_nb_status alch_nb_dihedrals(alch_nb_ctx* ctx, const double* d_pos, int32_t n_cv, const int32_t* d_idx,
+                                 double* d_xi, double* d_dxi, const double* d_mass_inv, double* d_msum,
+                                 const double* d_s, const double* d_kappa, double* d_u_dafed, double* d_forces) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (n_cv < 0 || (n_cv > 0 && (!d_pos || !d_idx || !d_xi || !d_dxi))) return ALCH_NB_E_INVALID_ARG;
+  if ((d_s == nullptr) != (d_kappa == nullptr)) return ALCH_NB_E_INVALID_ARG;
+  if (n_cv == 0) return ALCH_NB_OK;
+  HIPCHK(launch_dihedrals(ctx->stream, d_pos, n_cv, d_idx, d_xi, d_dxi, d_mass_inv, d_msum, d_s, d_kappa, d_u_dafed,
+                          d_forces, ctx->dev.reps, ctx->dev.atom_rep, ctx->N, ctx->dev.flags));
+  return ALCH_NB_OK;
 }
-alch_nb_status alch_nb_opes_update(alch_nb_ctx* ctx, double*, const double*, double*, int32_t) {
-  return ctx ? ALCH_NB_E_UNSUPPORTED : ALCH_NB_E_INVALID_ARG;
+
+int64_t alch_nb_opes_state_size(int32_t capacity) {
+  if (capacity < 1) return -1;
+  return (int64_t)OPES_HEADER + 2 * OPES_GRID_N + 2 * (int64_t)capacity;
 }
+
+alch_nb_status alch_nb_opes_init(alch_nb_ctx* ctx, double* d_state, int32_t capacity, double kT, double sigma,
+                                 double barrier_std, double barrier_expl, double theta0) {
+  if (!ctx || !d_state || capacity < 1 || !(kT > 0) || !(sigma > 0) || !(barrier_std > kT) ||
+      !(barrier_expl > kT) || !std::isfinite(theta0))
+    return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  HIPCHK(launch_opes_init(ctx->stream, d_state, capacity, kT, sigma, barrier_std, barrier_expl, theta0));
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_opes_update(alch_nb_ctx* ctx, double* d_state, const double* d_dudl, double* d_lambda_out,
+                                   int32_t deposit) {
+  if (!ctx || !d_state) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  HIPCHK(launch_opes(ctx->stream, d_state, d_dudl, d_lambda_out, deposit != 0));
+  return ALCH_NB_OK;
+}
+
 alch_nb_status alch_nb_autotune(alch_nb_ctx* ctx, const double*, const double*, int32_t) {
   return ctx ? ALCH_NB_E_UNSUPPORTED : ALCH_NB_E_INVALID_ARG;
 }

@@ -63,6 +63,7 @@ struct Dev {
   // static tables
   const int* atom_type;      // [N]
   const int* atom_grid;      // [N]
+  const int* atom_rep;       // [N] box of each atom
   const int* grid_atoms;     // [N] atoms of each grid, concatenated
   const GridInfo* grids;     // [G]
   const ReplicaInfo* reps;   // [K]
@@ -115,6 +116,7 @@ struct Dev {
   unsigned long long* ffix;  // [3*SC*64] fixed-point forces, component-major
   double* unit_acc;          // [U*NACC]
   LamState* lam;             // [K]
+  double* last_dudl;         // [K] dU/dlambda of the last forward
   double* pgrad_part;        // [PG_BLOCKS*3*T] parameter-gradient partials
   const float4* tp32;        // [T*T] type-pair sigma, 4 eps, k_e q q, 1/sigma^6 (rounded from FP64)
   const double4* tp64;       // [T*T]
@@ -123,5 +125,14 @@ struct Dev {
 enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6 };
 
 constexpr int kPgBlocks = 512;  // blocks of the parameter-gradient pass
+constexpr int kMaxTypes = 256;  // atom types supported by the parameter-gradient pass
+
+// lambda/OPES state layout (doubles): header, bias and derivative on the
+// output grid, kernel centres and Standard weights
+enum {
+  OPES_THETA = 0, OPES_LAMBDA = 1, OPES_DLAM = 2, OPES_U = 3, OPES_DU = 4, OPES_FTHETA = 5, OPES_KT = 6,
+  OPES_SIGMA = 7, OPES_DE_STD = 8, OPES_DE_EXPL = 9, OPES_N = 10, OPES_CAP = 11, OPES_S_STD = 12,
+  OPES_S_EXPL = 13, OPES_W_STD = 14, OPES_HEADER = 16, OPES_GRID_N = 101
+};
 
 }  // namespace anb

@@ -37,13 +37,16 @@ hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int pr
 hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int schedule, double* terms,
                            double* forces, double* dudl, long long* n_pairs);
 hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
-                              const double* g_energy, const TileShape& shape);
+                              const double* xin, const double* g_energy, double* d_sigma, double* d_sqrt_eps,
+                              double* d_charge);
 hipError_t launch_backward_finish(const Dev& d, hipStream_t st, int precision, const double* g_energy,
-                                  const double* dudl_saved, const double* forces_saved, double* d_pos,
-                                  double* d_lambda, double* d_sigma, double* d_sqrt_eps, double* d_charge);
+                                  double* d_pos, double* d_lambda);
 hipError_t launch_dihedrals(hipStream_t st, const double* pos, int n_cv, const int* idx, double* xi, double* dxi,
                             const double* mass_inv, double* msum, const double* s, const double* kappa,
-                            double* u_dafed, double* forces, const ReplicaInfo* reps, const int* atom_rep);
+                            double* u_dafed, double* forces, const ReplicaInfo* reps, const int* atom_rep,
+                            int n_atoms, unsigned int* flags);
+hipError_t launch_opes_init(hipStream_t st, double* state, int cap, double kT, double sigma, double de_std,
+                            double de_expl, double theta0);
 hipError_t launch_opes(hipStream_t st, double* state, const double* dudl, double* lambda_out, int deposit);
 
 // Fixed-point scale of the force accumulators (units per kcal/mol/A).

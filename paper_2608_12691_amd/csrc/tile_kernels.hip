@@ -662,6 +662,7 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
       if (terms)
         for (int j = 0; j < kNTerms; ++j) terms[k * kNTerms + j] = t[j];
       if (dudl) dudl[k] = t[9];
+      d.last_dudl[k] = t[9];
       if (n_pairs) n_pairs[k] = (long long)red[ACC_NPAIR][0];
     }
     return;

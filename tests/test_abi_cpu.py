@@ -19,7 +19,7 @@ def lib():
 
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "alch_nb.h")).read()
-    pat = r"^\s*(?:alch_nb_status|void|const char\s*\*|int32_t|double)\s*\*?\s*(alch_nb_[a-z0-9_]+)\s*\("
+    pat = r"^\s*(?:alch_nb_status|void|const char\s*\*|int32_t|int64_t|double)\s*\*?\s*(alch_nb_[a-z0-9_]+)\s*\("
     return sorted(set(re.findall(pat, src, flags=re.M)))
 
 
@@ -147,7 +147,9 @@ def test_strerror_and_misc(lib):
     assert lib.alch_nb_num_variants() >= 4
     assert lib.alch_nb_flops_per_pair(0) > 50
     assert lib.alch_nb_flops_per_pair(1) > lib.alch_nb_flops_per_pair(0)
-    offs = (ctypes.c_int32 * 16)()
-    assert lib.alch_nb_opes_layout(offs, 16) == 0
-    assert offs[15] + 101 == 16 + 4 * 101
+    offs = (ctypes.c_int32 * 18)()
+    assert lib.alch_nb_opes_layout(offs, 18) == 0
+    assert offs[0] == 0 and offs[15] == 16 and offs[17] == 16 + 2 * 101
     assert lib.alch_nb_opes_layout(offs, 3) == 1
+    assert lib.alch_nb_opes_state_size(100) == 16 + 2 * 101 + 200
+    assert lib.alch_nb_opes_state_size(0) == -1
