@@ -59,7 +59,7 @@ def run_path(ctx, traj, lams, W, K, torch, graph):
     from paper_2608_12691_amd import alchnb
     dev = traj.device
     pos = traj[0].clone()
-    lam = lams[0:1].clone()
+    lam = lams[0].clone()
     out = ctx.new_outputs()
     ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
     if graph:
@@ -67,7 +67,7 @@ def run_path(ctx, traj, lams, W, K, torch, graph):
 
     def step(t):
         pos.copy_(traj[t])
-        lam.copy_(lams[t:t + 1])
+        lam.copy_(lams[t])
         if graph:
             ctx.launch_step()
         else:
@@ -95,14 +95,14 @@ def count_pairs(ctx, traj, lams, W, K, torch):
     """Untimed pass over the same K calls: sum of evaluated pairs."""
     from paper_2608_12691_amd import alchnb
     pos = traj[0].clone()
-    lam = lams[0:1].clone()
+    lam = lams[0].clone()
     out = ctx.new_outputs(forces=False)
     acc = torch.zeros(1, dtype=torch.int64, device=traj.device)
     for t in range(W, W + K):
         pos.copy_(traj[t])
-        lam.copy_(lams[t:t + 1])
+        lam.copy_(lams[t])
         ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
-        acc += out["n_pairs"]
+        acc += out["n_pairs"].sum()
     torch.cuda.synchronize()
     return int(acc.item())
 
@@ -126,6 +126,32 @@ def cpu_baseline(w, traj_np, lams_np, W, sample_calls):
                        "%.1f s" % (sample_calls, W, W + sample_calls - 1, dt))
 
 
+def batched_vs_single(torch, steps, warmup, graph):
+    """16 boxes in one launch (lambda_k = k/15) vs one box of the same total size."""
+    from paper_2608_12691_amd import alchnb, systems
+    w4 = systems.make_config(4)
+    w1 = systems.single_box_like(w4)
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, w in (("batched16", w4), ("single_box", w1)):
+        ctx = alchnb.from_workload(w, precision=alchnb.FP32_FIXED)
+        x0 = np.concatenate([s_.positions for s_ in w.systems])
+        rng = np.random.Generator(np.random.PCG64(4242))
+        traj = torch.as_tensor(x0[None] + np.cumsum(rng.normal(0, 0.01, (warmup + steps, len(x0), 3)), axis=0),
+                               dtype=torch.float64, device=dev)
+        lam = torch.as_tensor(np.resize(w4.lambdas, len(w.systems)), dtype=torch.float64, device=dev)
+        lams = lam[None].repeat(warmup + steps, 1)
+        ctx.compute_checked(traj[0].clone(), lam.clone(), flags=alchnb.FORCE_REBUILD)
+        el, tile_ms, o, rb, _, _ = run_path(ctx, traj, lams, warmup, steps, torch, graph)
+        npairs = count_pairs(ctx, traj, lams, warmup, steps, torch)
+        out[name] = dict(atoms=int(len(x0)), boxes=len(w.systems), value=npairs / el, ms_per_step=1e3 * el / steps,
+                         tile_us=tile_ms * 1e3 if tile_ms else None, pairs_per_call=npairs / steps)
+        ctx.close()
+        log(name, out[name])
+    out["ratio"] = out["batched16"]["value"] / out["single_box"]["value"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +163,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-calls", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -158,16 +186,16 @@ def main():
     # all work on one non-default stream (graph capture needs one)
     torch.cuda.set_stream(torch.cuda.Stream(dev))
     traj = torch.as_tensor(traj_np, dtype=torch.float64, device=dev)
-    lams = torch.as_tensor(lams_np, dtype=torch.float64, device=dev)
+    lams = torch.as_tensor(lams_np, dtype=torch.float64, device=dev).reshape(-1, 1)
 
     res = {}
     for prec in ([alchnb.FP32_FIXED] if args.no_fp64 else [alchnb.FP32_FIXED, alchnb.FP64]):
         ctx = alchnb.from_workload(w, precision=prec, variant=args.variant)
         # size the list once (grows the capacity if the first build overflows)
         p0 = traj[0].clone()
-        ctx.compute_checked(p0, lams[0:1].clone(), flags=alchnb.FORCE_REBUILD)
+        ctx.compute_checked(p0, lams[0].clone(), flags=alchnb.FORCE_REBUILD)
         if args.autotune:
-            ctx.autotune(p0, lams[0:1].clone())
+            ctx.autotune(p0, lams[0].clone())
         elapsed, tile_ms, out, rebuilds, pos_last, lam_last = run_path(ctx, traj, lams, W, K, torch,
                                                                         args.mode == "graph")
         n_pairs = count_pairs(ctx, traj, lams, W, K, torch)
@@ -219,6 +247,8 @@ def main():
             "dudl_rel": abs(r32["dudl"] - r64["dudl"]) / max(abs(r64["dudl"]), 1e-300),
             "energy_rel": float(abs(r32["terms"][8] - r64["terms"][8]) / max(abs(r64["terms"][8]), 1e-300))}
     line["device_flags"] = {"fp32": r32["flags"], "fp64": res.get(alchnb.FP64, {}).get("flags")}
+    if not args.no_batched:
+        line["hrex16"] = batched_vs_single(torch, args.batched_steps, 20, args.mode == "graph")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, traj_np, lams_np, W, args.cpu_calls)
     print(json.dumps(line), flush=True)

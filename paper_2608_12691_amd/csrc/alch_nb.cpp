@@ -82,6 +82,7 @@ struct alch_nb_ctx {
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  double tuned_ms = 0;  // tile time of the variant chosen by the autotuner
 };
 
 static alch_nb_status hip_fail(alch_nb_ctx* c, hipError_t e) {
@@ -173,6 +174,9 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
 static double steiner(double a, double b, double c, double R) {
   return a * b * c + 2.0 * (a * b + b * c + c * a) * R + M_PI * (a + b + c) * R * R + 4.0 / 3.0 * M_PI * R * R * R;
 }
+
+static std::string tune_key(const alch_nb_ctx* ctx);
+static int tune_cache_lookup(const std::string& key);
 
 extern "C" {
 
@@ -409,6 +413,10 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
       ctx->tp32[(size_t)a * ctx->T + b] = make_float4((float)sg, (float)e4, (float)qq, (float)is6);
     }
   lay_out(ctx, nullptr, &ctx->dev);
+  if (p.variant < 0) {
+    const int v = tune_cache_lookup(tune_key(ctx));
+    if (v >= 0) ctx->variant = v;
+  }
   *out = ctx;
   return ALCH_NB_OK;
 }
@@ -699,8 +707,107 @@ alch_nb_status alch_nb_opes_update(alch_nb_ctx* ctx, double* d_state, const doub
   return ALCH_NB_OK;
 }
 
-alch_nb_status alch_nb_autotune(alch_nb_ctx* ctx, const double*, const double*, int32_t) {
-  return ctx ? ALCH_NB_E_UNSUPPORTED : ALCH_NB_E_INVALID_ARG;
+// ------------------------------------------------------------------ autotuner
+
+// Cache key: precision, schedule, log2 size bucket, boxes, density bucket
+// (atoms per nm^3) and cutoff (0.01 A).
+static std::string tune_key(const alch_nb_ctx* ctx) {
+  double vol = 0;
+  for (const auto& r : ctx->reps) vol += r.box[0] * r.box[1] * r.box[2];
+  const double rho = vol > 0 ? 1000.0 * ctx->N / vol : 0.0;
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "gfx950|p%d|s%d|n%d|k%d|rho%d|rc%d", ctx->p.precision, ctx->p.schedule,
+                (int)std::lround(std::log2(std::max(1, ctx->N))), ctx->K, (int)std::lround(rho / 10.0) * 10,
+                (int)std::lround(100.0 * ctx->p.cutoff));
+  return buf;
+}
+
+static int tune_cache_lookup(const std::string& key) {
+  const char* path = std::getenv("ALCHNB_TUNE_CACHE");
+  if (!path) return -1;
+  std::ifstream f(path);
+  if (!f) return -1;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string txt = ss.str();
+  const std::string pat = "\"" + key + "\":";
+  const size_t at = txt.find(pat);
+  if (at == std::string::npos) return -1;
+  const int v = std::atoi(txt.c_str() + at + pat.size());
+  return (v >= 0 && v < kNumVariants) ? v : -1;
+}
+
+static void tune_cache_store(const std::string& key, int variant) {
+  const char* path = std::getenv("ALCHNB_TUNE_CACHE");
+  if (!path) return;
+  std::string txt;
+  {
+    std::ifstream f(path);
+    if (f) {
+      std::stringstream ss;
+      ss << f.rdbuf();
+      txt = ss.str();
+    }
+  }
+  // entries are one per line: "key": variant
+  std::string out = "{\n";
+  std::istringstream in(txt);
+  std::string line;
+  bool first = true;
+  const std::string pat = "\"" + key + "\":";
+  while (std::getline(in, line)) {
+    const size_t q = line.find('"');
+    if (q == std::string::npos || line.find(pat) != std::string::npos) continue;
+    std::string ent = line.substr(q);
+    while (!ent.empty() && (ent.back() == ',' || ent.back() == ' ')) ent.pop_back();
+    out += (first ? "  " : ",\n  ") + ent;
+    first = false;
+  }
+  out += (first ? "  " : ",\n  ") + pat + " " + std::to_string(variant) + "\n}\n";
+  std::ofstream f(path, std::ios::trunc);
+  f << out;
+}
+
+alch_nb_status alch_nb_autotune(alch_nb_ctx* ctx, const double* d_pos, const double* d_lambda, int32_t reps) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!d_pos || !d_lambda || reps < 1) return ALCH_NB_E_INVALID_ARG;
+  alch_nb_status r = enqueue_compute(ctx, d_pos, d_lambda, ALCH_NB_AUTO_REBUILD, nullptr, false);
+  if (r != ALCH_NB_OK) return r;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int best = ctx->variant;
+  float best_ms = 1e30f;
+  for (int v = 0; v < kNumVariants; ++v) {
+    r = alch_nb_set_variant(ctx, v);
+    if (r != ALCH_NB_OK) break;
+    const TileShape sh = shape_of(ctx);
+    HIPCHK(launch_tile(ctx->dev, ctx->stream, ctx->pc, ctx->p.precision, ctx->p.schedule, sh, d_pos));  // warm-up
+    HIPCHK(hipEventRecord(e0, ctx->stream));
+    for (int k = 0; k < reps; ++k)
+      HIPCHK(launch_tile(ctx->dev, ctx->stream, ctx->pc, ctx->p.precision, ctx->p.schedule, sh, d_pos));
+    HIPCHK(hipEventRecord(e1, ctx->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = v;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (r != ALCH_NB_OK) return r;
+  r = alch_nb_set_variant(ctx, best);
+  if (r != ALCH_NB_OK) return r;
+  // restore the force accumulators and outputs of a regular evaluation
+  r = enqueue_compute(ctx, d_pos, d_lambda, 0, nullptr, false);
+  if (r != ALCH_NB_OK) return r;
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->tuned_ms = best_ms / reps;
+  tune_cache_store(tune_key(ctx), best);
+  return ALCH_NB_OK;
 }
 
 }  // extern "C"

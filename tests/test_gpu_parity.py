@@ -185,3 +185,42 @@ def test_graph_replay_matches_eager():
         a, b = to_numpy(gout), to_numpy(out)
         for k in ("forces", "terms", "dudl", "n_pairs"):
             assert np.array_equal(a[k], b[k]), (t, k)
+
+
+def test_autotune_keeps_parity_and_caches(tmp_path, monkeypatch):
+    w = workload(2)
+    monkeypatch.setenv("ALCHNB_TUNE_CACHE", str(tmp_path / "tune.json"))
+    ctx = _ctx(w, 0)
+    pos = ctx.positions(w.systems)
+    lam = ctx.lambdas([0.37])
+    ctx.autotune(pos, lam, reps=3)
+    v = ctx.get_stats()["variant"]
+    assert 0 <= v < ctx.lib.alch_nb_num_variants()
+    assert (tmp_path / "tune.json").exists()
+    res = to_numpy(ctx.compute_checked(pos, lam, flags=1))
+    ref = oracle_for(w, 0, 0.37, O.BEUTLER)
+    compare(res, [ref], w, [w.systems[0].positions], 0, _offsets(w), label="tuned")
+    # a new context with the same key picks the cached variant
+    ctx2 = _ctx(w, 0)
+    assert ctx2.get_stats()["variant"] == v
+    # every variant gives the same pair count and forces within tolerance
+    for vv in range(ctx.lib.alch_nb_num_variants()):
+        ctx.set_variant(vv)
+        r = to_numpy(ctx.compute_checked(pos, lam, flags=0))
+        compare(r, [ref], w, [w.systems[0].positions], 0, _offsets(w), label="variant %d" % vv)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+def test_config4_batched_replicas(precision):
+    """16 boxes of 2,000-12,000 atoms at lambda_k = k/15 in one launch; sampled boxes vs the oracle."""
+    w = workload(4)
+    ctx = _ctx(w, precision)
+    res, pos = _run(ctx, w, w.lambdas, flags=2)
+    off = _offsets(w)
+    for k in (0, 5, 10, 15):
+        sub = {kk: (v[off[k]:off[k + 1]] if kk == "forces" else v[k:k + 1]) for kk, v in res.items() if kk != "flags"}
+        ref = oracle_for(w, k, w.lambdas[k], O.BEUTLER)
+        one = S.Workload(w.name, [w.systems[k]], w.ff, w.cutoff, w.skin, w.switch_width, w.dsf_alpha, w.sc_alpha,
+                         w.lambdas[k:k + 1], w.seed)
+        compare(sub, [ref], one, [w.systems[k].positions], precision, np.array([0, off[k + 1] - off[k]]),
+                label="cfg4 box %d" % k)
