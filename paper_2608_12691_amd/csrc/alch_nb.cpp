@@ -56,11 +56,12 @@ struct alch_nb_ctx {
   int K = 0, N = 0, G = 0, C = 0, T = 0;
   double r_list = 0;
   // static tables (host copies)
-  std::vector<int> atom_type, atom_grid, grid_atoms, excl_start, excl_j, col_grid, atom_rep;
+  std::vector<int> atom_type, atom_grid, grid_atoms, excl_start, excl_j, col_grid, atom_rep, atom_comp;
   std::vector<GridInfo> grids;
   std::vector<float4> tp32;
   std::vector<double4> tp64;
   std::vector<ReplicaInfo> reps;
+  std::vector<double> sc_box;  // [SC*4]
   int sc_cap = 0, ent_cap = 0, unit_cap = 0;
   size_t ws_bytes = 0;
   // bound state
@@ -112,6 +113,8 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->atom_type = cv.take<int>(base, N);
   d->atom_grid = cv.take<int>(base, N);
   d->atom_rep = cv.take<int>(base, N);
+  d->atom_comp = cv.take<int>(base, N);
+  d->sc_box = cv.take<double4>(base, SC);
   d->grid_atoms = cv.take<int>(base, N);
   d->grids = cv.take<GridInfo>(base, ctx->G);
   d->reps = cv.take<ReplicaInfo>(base, K);
@@ -130,6 +133,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->col_sc = cv.take<int>(base, C);
   d->col_nsc = cv.take<int>(base, C);
   d->bucket = cv.take<int>(base, N);
+  d->bucket_z = cv.take<double>(base, N);
   d->sorted = cv.take<int>(base, N);
   d->sc_first = cv.take<int>(base, SC);
   d->sc_n = cv.take<int>(base, SC);
@@ -140,12 +144,16 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->cl_n = cv.take<int>(base, CL);
   d->slot_atom = cv.take<int>(base, SL);
   d->atom_slot = cv.take<int>(base, N);
+  d->slot_xw = cv.take<double4>(base, SL);
+  d->slot_comp = cv.take<int>(base, SL);
   d->se32 = cv.take<float2>(base, SL);
   d->se64 = cv.take<double2>(base, SL);
   d->q32 = cv.take<float>(base, SL);
   d->q64 = cv.take<double>(base, SL);
   d->sc_ecount = cv.take<int>(base, SC);
   d->sc_estart = cv.take<int>(base, SC);
+  d->strip_count = cv.take<int>(base, (size_t)SC * kStrips);
+  d->strip_start = cv.take<int>(base, (size_t)SC * kStrips);
   d->sc_ustart = cv.take<int>(base, SC);
   d->ent_jc = cv.take<int>(base, E);
   d->ent_info = cv.take<uint32_t>(base, E);
@@ -156,7 +164,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->ctr = cv.take<int>(base, 16);
   d->flags = cv.take<unsigned int>(base, 1);
   d->rebuild = cv.take<int>(base, 1);
-  d->barrier = cv.take<unsigned int>(base, 2);
+  d->barrier = cv.take<unsigned int>(base, kBarWords);
   d->pos32 = cv.take<float4>(base, SL);
   d->pos64 = cv.take<double4>(base, SL);
   d->ffix = cv.take<unsigned long long>(base, 3 * SL);
@@ -303,6 +311,27 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
     }
   }
 
+  // connected components of the exclusion graph: atoms in different
+  // components are never excluded from each other (fast test in the masks)
+  {
+    std::vector<int> parent(ctx->N);
+    for (int i = 0; i < ctx->N; ++i) parent[i] = i;
+    auto find = [&](int x) {
+      while (parent[x] != x) {
+        parent[x] = parent[parent[x]];
+        x = parent[x];
+      }
+      return x;
+    };
+    for (int i = 0; i < ctx->N; ++i)
+      for (int e = ctx->excl_start[i]; e < ctx->excl_start[i + 1]; ++e) {
+        const int a = find(i), b = find(ctx->excl_j[e]);
+        if (a != b) parent[std::max(a, b)] = std::min(a, b);
+      }
+    ctx->atom_comp.resize(ctx->N);
+    for (int i = 0; i < ctx->N; ++i) ctx->atom_comp[i] = find(i);
+  }
+
   // grids: per box, the solute group then the environment group
   const double margin = 1.0;  // position jitter allowance in the cluster size estimate
   double ent_est = 0;
@@ -379,6 +408,10 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
   ctx->G = (int)ctx->grids.size();
   ctx->C = (int)ctx->col_grid.size();
   ctx->sc_cap = std::max(1, sc_base);
+  ctx->sc_box.assign(4 * (size_t)ctx->sc_cap, 0.0);
+  for (const GridInfo& g : ctx->grids)
+    for (int s = g.sc_base; s < g.sc_base + g.sc_cap; ++s)
+      for (int k = 0; k < 3; ++k) ctx->sc_box[4 * (size_t)s + k] = ctx->reps[g.replica].box[k];
   const double fac = p.list_capacity_factor > 0 ? p.list_capacity_factor : 1.0;
   const double ent_cap = std::ceil(fac * (1.6 * ent_est + 64.0 * ctx->sc_cap + 1024.0));
   if (ent_cap > 2.0e9 / kScCl) {
@@ -454,7 +487,7 @@ alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* st
     const int per_cu = list_fused_max_blocks();
     const char* env = std::getenv("ALCHNB_LIST_KERNELS");
     const bool split = env && std::strcmp(env, "split") == 0;
-    ctx->fused_blocks = (!split && per_cu >= 1 && n_cu > 0) ? n_cu * std::min(per_cu, 2) : 0;
+    ctx->fused_blocks = (!split && per_cu >= 1 && n_cu > 0) ? n_cu : 0;  // one block of 8 waves per CU
   }
   auto up = [&](const void* dst, const void* src, size_t n) -> hipError_t {
     if (n == 0) return hipSuccess;
@@ -463,6 +496,8 @@ alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* st
   HIPCHK(up(d.atom_type, ctx->atom_type.data(), sizeof(int) * ctx->N));
   HIPCHK(up(d.atom_grid, ctx->atom_grid.data(), sizeof(int) * ctx->N));
   HIPCHK(up(d.atom_rep, ctx->atom_rep.data(), sizeof(int) * ctx->N));
+  HIPCHK(up(d.atom_comp, ctx->atom_comp.data(), sizeof(int) * ctx->N));
+  HIPCHK(up(d.sc_box, ctx->sc_box.data(), sizeof(double) * ctx->sc_box.size()));
   HIPCHK(up(d.grid_atoms, ctx->grid_atoms.data(), sizeof(int) * ctx->grid_atoms.size()));
   HIPCHK(up(d.grids, ctx->grids.data(), sizeof(GridInfo) * ctx->G));
   HIPCHK(up(d.reps, ctx->reps.data(), sizeof(ReplicaInfo) * ctx->K));

@@ -19,6 +19,12 @@ namespace anb {
 constexpr int kCl = 8;           // atom slots per cluster
 constexpr int kScCl = 8;         // clusters per super-cluster
 constexpr int kSc = 64;          // atom slots per super-cluster
+// grid barrier of the fused list build: word 0 top arrival count, word 1
+// generation, word kBarStride*(g+1) arrival count of block group g
+constexpr int kBarGroups = 8;
+constexpr int kBarStride = 16;  // counters on separate 64-byte lines
+constexpr int kBarWords = kBarStride * (kBarGroups + 1);
+constexpr int kStrips = 8;       // search waves per super-cluster (neighbour columns dealt round-robin)
 constexpr double kKe = 332.06371;
 constexpr int kNTerms = 10;  // energy-term slots per box
 
@@ -64,6 +70,8 @@ struct Dev {
   const int* atom_type;      // [N]
   const int* atom_grid;      // [N]
   const int* atom_rep;       // [N] box of each atom
+  const int* atom_comp;      // [N] connected component of the exclusion graph (global id)
+  const double4* sc_box;     // [SC] box lengths of the SC's replica (SC ranges are fixed per grid)
   const int* grid_atoms;     // [N] atoms of each grid, concatenated
   const GridInfo* grids;     // [G]
   const ReplicaInfo* reps;   // [K]
@@ -82,6 +90,7 @@ struct Dev {
   int* col_fill;             // [C]
   int* col_sc;               // [C] first SC of the column
   int* col_nsc;              // [C]
+  double* bucket_z;          // [N] wrapped z of the bucket's atom (sort keys)
   int* bucket;               // [N]
   int* sorted;               // [N]
   int* sc_first;             // [SC] offset into sorted
@@ -93,12 +102,16 @@ struct Dev {
   int* cl_n;                 // [SC*8]
   int* slot_atom;            // [SC*64] atom index or -1
   int* atom_slot;            // [N]
+  double4* slot_xw;          // [SC*64] build-time wrapped position of the slot's atom
+  int* slot_comp;            // [SC*64] exclusion component of the slot's atom (-1 = padding)
   float2* se32;              // [SC*64] sigma/2, 2 sqrt(eps)
   double2* se64;             // [SC*64]
   float* q32;                // [SC*64] q sqrt(k_e)
   double* q64;               // [SC*64]
   int* sc_ecount;            // [SC]
   int* sc_estart;            // [SC]
+  int* strip_count;          // [SC*kStrips] entries found by each search wave
+  int* strip_start;          // [SC*kStrips]
   int* sc_ustart;            // [SC]
   int* ent_jc;               // [E]
   uint32_t* ent_info;        // [E]
@@ -109,7 +122,7 @@ struct Dev {
   int* ctr;                  // [16] counters, see CTR_*
   unsigned int* flags;       // [1] sticky flags
   int* rebuild;              // [1]
-  unsigned int* barrier;     // [2] grid-barrier arrival count and generation
+  unsigned int* barrier;     // [kBarWords] grid barrier: top count, generation, group counts
   // per call
   float4* pos32;             // [SC*64] local x, y, z, q
   double4* pos64;            // [SC*64]

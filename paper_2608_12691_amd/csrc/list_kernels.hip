@@ -18,7 +18,8 @@
 
 namespace anb {
 
-constexpr int kBlk = 256;
+constexpr int kBlk = 512;          // threads per block of every list kernel
+constexpr int kWpb = kBlk / 64;     // waves per block
 
 __device__ inline bool rebuild_on(const Dev& d) { return __atomic_load_n(d.rebuild, __ATOMIC_RELAXED) != 0; }
 
@@ -35,17 +36,17 @@ __device__ inline int gwaves() { return gridDim.x * (blockDim.x >> 6); }
 // Exclusive scan of one int per thread over the block; *total = block sum.
 __device__ int block_exclusive_scan(int v, int* total) {
   __shared__ int buf[kBlk];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, nt = blockDim.x;
   buf[t] = v;
   __syncthreads();
-  for (int off = 1; off < kBlk; off <<= 1) {
+  for (int off = 1; off < nt; off <<= 1) {
     const int add = t >= off ? buf[t - off] : 0;
     __syncthreads();
     buf[t] += add;
     __syncthreads();
   }
   const int incl = buf[t];
-  *total = buf[kBlk - 1];
+  *total = buf[nt - 1];
   __syncthreads();
   return incl - v;
 }
@@ -53,7 +54,7 @@ __device__ int block_exclusive_scan(int v, int* total) {
 // Exclusive scan of src[0..n) into dst by one block; returns the total.
 // src and dst may alias (values are read before they are overwritten).
 __device__ int block_scan_array(const int* src, int* dst, int n) {
-  const int per = (n + kBlk - 1) / kBlk;
+  const int per = (n + blockDim.x - 1) / blockDim.x;
   const int lo = threadIdx.x * per;
   const int hi = min(n, lo + per);
   int s = 0;
@@ -71,15 +72,28 @@ __device__ int block_scan_array(const int* src, int* dst, int n) {
 
 // ------------------------------------------------------------ phases
 
-__device__ void ph_begin(const Dev& d) {
-  if (gtid() == 0) d.ctr[CTR_TILES] = 0;
-  for (int c = gtid(); c < d.n_cols; c += gthreads()) {
-    d.col_count[c] = 0;
-    d.col_fill[c] = 0;
-  }
+
+constexpr int kLdsCols = 4096;  // columns counted in LDS before one global add per block and column
+
+// One LDS pool shared by the binning phases (a phase ends with a block
+// barrier before the next one reuses it).
+__device__ inline int* lds_pool() {
+  __shared__ int pool[2 * kLdsCols];
+  return pool;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 __device__ void ph_bin(const Dev& d, const double* __restrict__ pos) {
+  int* lcnt = lds_pool();
+  const bool lds = d.n_cols <= kLdsCols;
+  if (lds)
+    for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x) lcnt[c] = 0;
+  __syncthreads();
   for (int a = gtid(); a < d.n_atoms; a += gthreads()) {
     const GridInfo gi = d.grids[d.atom_grid[a]];
     const ReplicaInfo& rp = d.reps[gi.replica];
@@ -95,13 +109,18 @@ __device__ void ph_bin(const Dev& d, const double* __restrict__ pos) {
     cy = cy < 0 ? 0 : (cy >= gi.ncy ? gi.ncy - 1 : cy);
     const int col = gi.col_base + cx + gi.ncx * cy;
     d.atom_col[a] = col;
-    atomicAdd(&d.col_count[col], 1);
+    if (lds) atomicAdd(&lcnt[col], 1);
+    else atomicAdd(&d.col_count[col], 1);
   }
+  __syncthreads();
+  if (lds)
+    for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x)
+      if (lcnt[c]) atomicAdd(&d.col_count[c], lcnt[c]);
+  __syncthreads();
 }
 
-// Block 0 only: column offsets, SC allocation per column, SC table.
+// One block: column offsets, SC allocation per column, SC table.
 __device__ void ph_scan_cols(const Dev& d) {
-  if (blockIdx.x != 0) return;
   const int C = d.n_cols;
   block_scan_array(d.col_count, d.col_start, C);
   for (int c = threadIdx.x; c < C; c += blockDim.x) d.col_nsc[c] = (d.col_count[c] + kSc - 1) / kSc;
@@ -131,52 +150,85 @@ __device__ void ph_scan_cols(const Dev& d) {
   for (int c = threadIdx.x; c < C; c += blockDim.x) d.col_fill[c] = 0;
 }
 
+// Atoms into their column's bucket (order inside a bucket is arbitrary; the
+// rank sort fixes it).  Each block reserves one range per column.
 __device__ void ph_scatter(const Dev& d) {
+  int* lcnt = lds_pool();
+  int* lbase = lcnt + kLdsCols;
+  const bool lds = d.n_cols <= kLdsCols;
+  if (!lds) {
+    for (int a = gtid(); a < d.n_atoms; a += gthreads()) {
+      const int col = d.atom_col[a];
+      const int p = d.col_start[col] + atomicAdd(&d.col_fill[col], 1);
+      d.bucket[p] = a;
+      d.bucket_z[p] = d.xw[3 * a + 2];
+    }
+    return;
+  }
+  for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x) lcnt[c] = 0;
+  __syncthreads();
+  for (int a = gtid(); a < d.n_atoms; a += gthreads()) atomicAdd(&lcnt[d.atom_col[a]], 1);
+  __syncthreads();
+  for (int c = threadIdx.x; c < d.n_cols; c += blockDim.x) {
+    lbase[c] = lcnt[c] ? d.col_start[c] + atomicAdd(&d.col_fill[c], lcnt[c]) : 0;
+    lcnt[c] = 0;
+  }
+  __syncthreads();
   for (int a = gtid(); a < d.n_atoms; a += gthreads()) {
     const int col = d.atom_col[a];
-    const int p = d.col_start[col] + atomicAdd(&d.col_fill[col], 1);
+    const int p = lbase[col] + atomicAdd(&lcnt[col], 1);
     d.bucket[p] = a;
+    d.bucket_z[p] = d.xw[3 * a + 2];
   }
+  __syncthreads();
 }
 
-// Rank sort of each column by (wrapped z, atom index); one block per column.
+// Rank sort of each column by (wrapped z, atom index).  One wave per 64
+// bucket positions of a column (the column's future SCs): each lane counts
+// the column's atoms that precede its own, the column streamed through a
+// 64-entry LDS window with the next window prefetched into registers.
 __device__ void ph_sort_cols(const Dev& d) {
-  constexpr int CH = 1024;
-  __shared__ double kz[CH];
-  __shared__ int ka[CH];
-  for (int c = blockIdx.x; c < d.n_cols; c += gridDim.x) {
-    const int n = d.col_count[c];
-    const int base = d.col_start[c];
-    for (int ib = 0; ib < n; ib += blockDim.x) {
-      const int i = ib + threadIdx.x;
-      const bool have = i < n;
-      int ai = 0;
-      double zi = 0;
-      if (have) {
-        ai = d.bucket[base + i];
-        zi = d.xw[3 * ai + 2];
-      }
-      int rank = 0;
-      for (int jb = 0; jb < n; jb += CH) {
-        __syncthreads();
-        for (int j = threadIdx.x; j < CH && jb + j < n; j += blockDim.x) {
-          const int aj = d.bucket[base + jb + j];
-          ka[j] = aj;
-          kz[j] = d.xw[3 * aj + 2];
+  __shared__ double kz[kBlk];
+  __shared__ int ka[kBlk];
+  const int lane = threadIdx.x & 63;
+  double* wz = kz + (threadIdx.x & ~63);
+  int* wa = ka + (threadIdx.x & ~63);
+  for (int s = gwave(); s < d.sc_cap; s += gwaves()) {
+    const int n_i = d.sc_n[s];
+    if (n_i == 0) continue;
+    const int c = d.sc_col[s];
+    const int base = d.col_start[c], n = d.col_count[c];
+    const bool have = lane < n_i;
+    const int p = d.sc_first[s] + lane;
+    const int ai = have ? d.bucket[p] : 0;
+    const double zi = have ? d.bucket_z[p] : 0.0;
+    int aj = lane < n ? d.bucket[base + lane] : 0;
+    double zj = lane < n ? d.bucket_z[base + lane] : 0.0;
+    int rank = 0;
+    for (int jb = 0; jb < n; jb += 64) {
+      wave_sync();
+      wz[lane] = zj;
+      wa[lane] = aj;
+      wave_sync();
+      const int jn = jb + 64 + lane;
+      aj = jn < n ? d.bucket[base + jn] : 0;
+      zj = jn < n ? d.bucket_z[base + jn] : 0.0;
+      const int m = min(64, n - jb);
+      int j = 0;
+      for (; j + 8 <= m; j += 8) {
+        double zz[8];
+        int aa[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          zz[u] = wz[j + u];
+          aa[u] = wa[j + u];
         }
-        __syncthreads();
-        if (have) {
-          const int m = min(CH, n - jb);
-          for (int j = 0; j < m; ++j) {
-            const double zj = kz[j];
-            const int aj = ka[j];
-            rank += (zj < zi || (zj == zi && aj < ai)) ? 1 : 0;
-          }
-        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rank += (zz[u] < zi || (zz[u] == zi && aa[u] < ai)) ? 1 : 0;
       }
-      if (have) d.sorted[base + rank] = ai;
+      for (; j < m; ++j) rank += (wz[j] < zi || (wz[j] == zi && wa[j] < ai)) ? 1 : 0;
     }
-    __syncthreads();
+    if (have) d.sorted[base + rank] = ai;
   }
 }
 
@@ -242,6 +294,8 @@ __device__ void ph_build_sc(const Dev& d) {
     }
     const int sl = s * kSc + l;
     d.slot_atom[sl] = a;
+    d.slot_xw[sl] = make_double4(w[0], w[1], w[2], 0.0);
+    d.slot_comp[sl] = a >= 0 ? d.atom_comp[a] : -1;
     if (a >= 0) {
       d.atom_slot[a] = sl;
       const int t = d.atom_type[a];
@@ -298,17 +352,20 @@ __device__ inline double gap1(double ilo, double ihi, double jlo, double jhi) {
   return fmax(0.0, fmax(jlo - ihi, ilo - jhi));
 }
 
-// Cluster-pair search, one wave per i-SC.  Candidates are walked in a fixed
-// order: j-grid, x shift and column, y shift and column, j-SC in z order, z
-// shift, then j-cluster.  WRITE = false counts, true writes.
+// Cluster-pair search, kStrips waves per i-SC: the neighbour columns that
+// pass the x-y test are dealt round-robin to the waves of the SC.  Each wave
+// walks its candidates in a fixed order: j-grid, x shift and column, y shift
+// and column, j-SC in z order, z shift, then j-cluster; its entries follow
+// those of the SC's lower strips.  WRITE = false counts, true writes.
 template <bool WRITE>
 __device__ void ph_search(const Dev& d, double rlm) {
   const double rl2 = rlm * rlm;
   const int lane = threadIdx.x & 63;
   const int ic = lane >> 3, jcq = lane & 7;  // search layout: (i-cluster, j-cluster)
-  for (int s = gwave(); s < d.sc_cap; s += gwaves()) {
+  for (int sw = gwave(); sw < d.sc_cap * kStrips; sw += gwaves()) {
+    const int s = sw / kStrips, strip = sw % kStrips;
     if (d.sc_n[s] == 0) {
-      if (!WRITE && lane == 0) d.sc_ecount[s] = 0;
+      if (!WRITE && lane == 0) d.strip_count[sw] = 0;
       continue;
     }
     const GridInfo gi = d.grids[d.col_grid[d.sc_col[s]]];
@@ -323,8 +380,8 @@ __device__ void ph_search(const Dev& d, double rlm) {
       cilo[k] = d.cl_bbox[icl * 6 + k];
       cihi[k] = d.cl_bbox[icl * 6 + 3 + k];
     }
-    int count = 0;
-    const int wbase = WRITE ? d.sc_estart[s] : 0;
+    int count = 0, n_col = 0;
+    const int wbase = WRITE ? d.strip_start[sw] : 0;
     for (int gj_idx = rp.grid0; gj_idx < rp.grid0 + rp.n_grids; ++gj_idx) {
       const GridInfo gj = d.grids[gj_idx];
       if (gj.n_atoms == 0 || gj.sc_base + gj.sc_cap <= s) continue;
@@ -340,24 +397,38 @@ __device__ void ph_search(const Dev& d, double rlm) {
               const double ylo = cy * gj.wy + syi * L[1], yhi = ylo + gj.wy;
               const double gy = gap1(ilo[1], ihi[1], ylo, yhi);
               if (gx * gx + gy * gy >= rl2) continue;
+              if (n_col++ % kStrips != strip) continue;
               const int col = gj.col_base + cx + gj.ncx * cy;
-              const int js0 = d.col_sc[col], nsc = d.col_nsc[col];
-              for (int js = max(js0, s); js < js0 + nsc; ++js) {
-                for (int szi = -1; szi <= 1; ++szi) {
+              const int jsb = max(d.col_sc[col], s), jse = d.col_sc[col] + d.col_nsc[col];
+              const int m = (jse - jsb) * 3;  // candidates (j-SC, z shift), j-SC major
+              for (int k0 = 0; k0 < m; k0 += 64) {
+                // lane-parallel super-cluster box test
+                const int k = k0 + lane;
+                bool pass = false;
+                if (k < m) {
+                  const int js = jsb + k / 3, szi = k % 3 - 1;
                   const double sh[3] = {sxi * L[0], syi * L[1], szi * L[2]};
                   double g2 = 0;
-                  for (int k = 0; k < 3; ++k) {
-                    const double g = gap1(ilo[k], ihi[k], d.sc_bbox[js * 6 + k] + sh[k], d.sc_bbox[js * 6 + 3 + k] + sh[k]);
+                  for (int q = 0; q < 3; ++q) {
+                    const double g = gap1(ilo[q], ihi[q], d.sc_bbox[js * 6 + q] + sh[q], d.sc_bbox[js * 6 + 3 + q] + sh[q]);
                     g2 += g * g;
                   }
-                  if (g2 >= rl2) continue;
+                  pass = g2 < rl2;
+                }
+                unsigned long long P = __ballot(pass);
+                while (P) {
+                  const int b = __ffsll((long long)P) - 1;
+                  P &= P - 1;
+                  const int js = jsb + (k0 + b) / 3, szi = (k0 + b) % 3 - 1;
+                  const double sh[3] = {sxi * L[0], syi * L[1], szi * L[2]};
+                  // cluster level: lane (ic, jcq)
                   const int jcl = js * kScCl + jcq;
                   bool ok = i_ok && d.cl_n[jcl] > 0 && jcl >= icl;
                   if (ok) {
                     double c2 = 0;
-                    for (int k = 0; k < 3; ++k) {
-                      const double g = gap1(cilo[k], cihi[k], d.cl_bbox[jcl * 6 + k] + sh[k],
-                                            d.cl_bbox[jcl * 6 + 3 + k] + sh[k]);
+                    for (int q = 0; q < 3; ++q) {
+                      const double g = gap1(cilo[q], cihi[q], d.cl_bbox[jcl * 6 + q] + sh[q],
+                                            d.cl_bbox[jcl * 6 + 3 + q] + sh[q]);
                       c2 += g * g;
                     }
                     ok = c2 < rl2;
@@ -366,7 +437,7 @@ __device__ void ph_search(const Dev& d, double rlm) {
                   if (M == 0) continue;
                   // lane j (0..7) gathers the i-cluster mask of j-cluster j
                   uint32_t imask = 0;
-                  for (int b = 0; b < kScCl; ++b) imask |= (uint32_t)((M >> (b * 8 + (lane & 7))) & 1ull) << b;
+                  for (int bb = 0; bb < kScCl; ++bb) imask |= (uint32_t)((M >> (bb * 8 + (lane & 7))) & 1ull) << bb;
                   const bool emit = lane < 8 && imask != 0;
                   const unsigned long long E = __ballot(emit);
                   if (WRITE && emit) {
@@ -385,15 +456,22 @@ __device__ void ph_search(const Dev& d, double rlm) {
             }
         }
     }
-    if (!WRITE && lane == 0) d.sc_ecount[s] = count;
+    if (!WRITE && lane == 0) d.strip_count[sw] = count;
   }
 }
 
-// Block 0 only: entry offsets per SC and the capacity check.
+// One block: entry offsets per search strip and per SC, capacity check.
 __device__ void ph_scan_entries(const Dev& d) {
-  if (blockIdx.x != 0) return;
-  const int total = block_scan_array(d.sc_ecount, d.sc_estart, d.sc_cap);
+  const int total = block_scan_array(d.strip_count, d.strip_start, d.sc_cap * kStrips);
+  for (int s = threadIdx.x; s < d.sc_cap; s += blockDim.x) {
+    int c = 0;
+    for (int p = 0; p < kStrips; ++p) c += d.strip_count[s * kStrips + p];
+    d.sc_ecount[s] = c;
+    d.sc_estart[s] = d.strip_start[s * kStrips];
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    d.ctr[CTR_TILES] = 0;  // summed by the mask phase
     d.ctr[CTR_ENT_NEED] = total;
     if (total > d.ent_cap) atomicOr(d.flags, 16u);
     d.ctr[CTR_NENT] = total > d.ent_cap ? 0 : total;
@@ -401,9 +479,8 @@ __device__ void ph_scan_entries(const Dev& d) {
   __syncthreads();
 }
 
-// Block 0 only: work units of at most epu entries per SC, replica ranges.
+// One block: work units of at most epu entries per SC, replica ranges.
 __device__ void ph_units(const Dev& d, int epu) {
-  if (blockIdx.x != 0) return;
   const bool ok_all = d.ctr[CTR_NENT] == d.ctr[CTR_ENT_NEED];
   const int n = d.sc_cap;
   for (int s = threadIdx.x; s < n; s += blockDim.x) d.sc_ustart[s] = ok_all ? (d.sc_ecount[s] + epu - 1) / epu : 0;
@@ -460,47 +537,53 @@ __device__ void ph_masks(const Dev& d, double rl2) {
   const int lane = threadIdx.x & 63;
   const int il = lane & 7, jl = lane >> 3;
   const int n_ent = d.ctr[CTR_NENT];
+  int tiles = 0;  // 64-lane pair tiles of this wave's entries
   for (int e = gwave(); e < n_ent; e += gwaves()) {
     const int s = d.ent_isc[e];
     const int jc = d.ent_jc[e];
     const uint32_t info = d.ent_info[e];
-    uint32_t imask = info & 0xffu;
+    const uint32_t imask = info & 0xffu;
     const int code = (int)((info >> 16) & 31u);
-    const int aj = d.slot_atom[jc * kCl + jl];
-    double sh[3] = {0, 0, 0};
-    if (aj >= 0) {
-      const ReplicaInfo& rp = d.reps[d.grids[d.atom_grid[aj]].replica];
-      sh[0] = (code % 3 - 1) * rp.box[0];
-      sh[1] = ((code / 3) % 3 - 1) * rp.box[1];
-      sh[2] = (code / 9 - 1) * rp.box[2];
+    const int jsl = jc * kCl + jl;
+    const int cj = d.slot_comp[jsl];
+    const double4 wj = d.slot_xw[jsl];
+    const double4 L = d.sc_box[s];
+    const double shx = (code % 3 - 1) * L.x, shy = ((code / 3) % 3 - 1) * L.y, shz = (code / 9 - 1) * L.z;
+    const double xj = wj.x + shx, yj = wj.y + shy, zj = wj.z + shz;
+    bool ok[kScCl];
+    // independent loads for all i-clusters first, exclusion searches only
+    // for pairs inside one exclusion component
+#pragma unroll
+    for (int c = 0; c < kScCl; ++c) {
+      const int isl = (s * kScCl + c) * kCl + il;
+      const int ci = d.slot_comp[isl];
+      const double4 wi = d.slot_xw[isl];
+      const double vx = xj - wi.x, vy = yj - wi.y, vz = zj - wi.z;
+      const double r2 = vx * vx + vy * vy + vz * vz;
+      ok[c] = (imask & (1u << c)) && ci >= 0 && cj >= 0 && (s * kScCl + c != jc || il < jl) && r2 < rl2;
+      if (ok[c] && ci == cj) ok[c] = !is_excluded(d, d.slot_atom[isl], d.slot_atom[jsl]);
     }
     uint32_t keep = 0;
+    unsigned long long mine = 0;
+#pragma unroll
     for (int c = 0; c < kScCl; ++c) {
-      bool ok = false;
-      if (imask & (1u << c)) {
-        const int icl = s * kScCl + c;
-        const int ai = d.slot_atom[icl * kCl + il];
-        if (ai >= 0 && aj >= 0 && (icl != jc || il < jl)) {
-          double r2 = 0;
-          for (int k = 0; k < 3; ++k) {
-            const double v = d.xw[3 * aj + k] + sh[k] - d.xw[3 * ai + k];
-            r2 += v * v;
-          }
-          ok = r2 < rl2 && !is_excluded(d, ai, aj);
-        }
-      }
-      const unsigned long long M = __ballot(ok);
+      const unsigned long long M = __ballot(ok[c]);
       if (M) keep |= 1u << c;
-      if (lane == 0) d.ent_mask[(size_t)e * kScCl + c] = M;
+      if (lane == c) mine = M;
     }
-    if (lane == 0) {
-      if (keep != imask) d.ent_info[e] = (info & ~0xffu) | keep;
-      atomicAdd(&d.ctr[CTR_TILES], __popc(keep));  // 64-lane pair tiles of this list
-    }
+    if (lane < kScCl) d.ent_mask[(size_t)e * kScCl + lane] = mine;
+    if (lane == 0 && keep != imask) d.ent_info[e] = (info & ~0xffu) | keep;
+    tiles += __popc(keep);
   }
+  // one counter update per wave: a single contended address would
+  // serialise tens of thousands of atomics
+  if (lane == 0 && tiles) atomicAdd(&d.ctr[CTR_TILES], tiles);
 }
 
+// Column counters start at zero for the next build (the workspace is
+// cleared when it is bound, so the first build finds them zero too).
 __device__ void ph_end(const Dev& d) {
+  for (int c = gtid(); c < d.n_cols; c += gthreads()) d.col_count[c] = 0;
   if (gtid() == 0) {
     d.ctr[CTR_NBUILD] += 1;
     __atomic_store_n(d.rebuild, 0, __ATOMIC_RELAXED);
@@ -510,7 +593,6 @@ __device__ void ph_end(const Dev& d) {
 // ------------------------------------------------------------ kernels
 
 #define GATED if (!rebuild_on(d)) return
-__global__ void __launch_bounds__(kBlk) k_begin(Dev d) { GATED; ph_begin(d); }
 __global__ void __launch_bounds__(kBlk) k_bin(Dev d, const double* pos) { GATED; ph_bin(d, pos); }
 __global__ void __launch_bounds__(kBlk) k_scan_cols(Dev d) { GATED; ph_scan_cols(d); }
 __global__ void __launch_bounds__(kBlk) k_scatter(Dev d) { GATED; ph_scatter(d); }
@@ -529,37 +611,60 @@ __global__ void __launch_bounds__(kBlk) k_end(Dev d) { GATED; ph_end(d); }
 
 static inline int clampi(long long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); }
 
-// Grid barrier for the fused list build.  Blocks arrive on a counter and
-// wait for a generation change; the wait is bounded, and a block that gives
-// up raises ALCH_NB_FLAG_BARRIER_TIMEOUT and proceeds, so every wave always
-// finishes.  The grid is sized on the host to fit the device at once.
-__device__ inline void grid_barrier(const Dev& d, unsigned int& gen) {
+// Grid barrier for the fused list build.  Every wave waits for its own
+// stores, then one thread per block writes back its XCD's L2 and arrives on
+// one of eight group counters (blocks b = g mod 8); the last block of a
+// group arrives on the top counter, and the last group's block runs the
+// optional one-block section SERIAL (a scan) before it opens the next
+// generation.  Waiters poll the generation with relaxed loads and acquire
+// once.  The wait is bounded: a block that gives up raises
+// ALCH_NB_FLAG_BARRIER_TIMEOUT and proceeds, so every wave finishes.  The
+// grid is sized on the host to fit the device at once.
+template <class Serial>
+__device__ inline void grid_barrier(const Dev& d, unsigned int& gen, Serial serial) {
+  __shared__ int is_last;
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  unsigned int* bar = d.barrier;
   if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned int* bar = d.barrier;
-    const unsigned int g = gen;
-    if (atomicAdd(&bar[0], 1u) == gridDim.x - 1) {
-      atomicExch(&bar[0], 0u);
-      __threadfence();
-      atomicAdd(&bar[1], 1u);
-    } else {
-      unsigned int spins = 0;
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(8);
-        if (++spins > (1u << 22)) {
-          atomicOr(d.flags, 32u);
-          break;
-        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned int grp = blockIdx.x % kBarGroups;
+    const unsigned int n_grp = (gridDim.x - grp + kBarGroups - 1) / kBarGroups;
+    const unsigned int n_top = min(gridDim.x, (unsigned int)kBarGroups);
+    int last = 0;
+    unsigned int* gc = bar + kBarStride * (grp + 1);
+    if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == n_grp - 1) {
+      __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == n_top - 1;
+    }
+    is_last = last;
+  }
+  __syncthreads();
+  if (is_last) {
+    serial();
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  } else if (threadIdx.x == 0) {
+    unsigned int spins = 0;
+    while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > (1u << 24)) {
+        atomicOr(d.flags, 32u);
+        break;
       }
     }
-    __threadfence();
-    gen = g + 1;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
+  gen += 1;
   __syncthreads();
 }
 
-// The whole list build in one launch (phases separated by grid barriers).
+// The whole list build in one launch (phases separated by grid barriers;
+// the one-block scans run inside the barriers).
 __global__ void __launch_bounds__(kBlk) k_list_fused(Dev d, const double* __restrict__ pos, double rlm, double rl2,
                                                      int epu) {
   if (!rebuild_on(d)) return;
@@ -567,27 +672,22 @@ __global__ void __launch_bounds__(kBlk) k_list_fused(Dev d, const double* __rest
   if (threadIdx.x == 0) gen_s = __hip_atomic_load(&d.barrier[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
   unsigned int gen = gen_s;
-  ph_begin(d);
-  grid_barrier(d, gen);
+  auto none = [] {};
   ph_bin(d, pos);
-  grid_barrier(d, gen);
-  ph_scan_cols(d);
-  grid_barrier(d, gen);
+  grid_barrier(d, gen, [&] { ph_scan_cols(d); });
   ph_scatter(d);
-  grid_barrier(d, gen);
+  grid_barrier(d, gen, none);
   ph_sort_cols(d);
-  grid_barrier(d, gen);
+  grid_barrier(d, gen, none);
   ph_build_sc(d);
-  grid_barrier(d, gen);
+  grid_barrier(d, gen, none);
   ph_search<false>(d, rlm);
-  grid_barrier(d, gen);
-  ph_scan_entries(d);
-  grid_barrier(d, gen);
+  grid_barrier(d, gen, [&] { ph_scan_entries(d); });
   ph_search<true>(d, rlm);
-  grid_barrier(d, gen);
-  ph_units(d, epu);
+  grid_barrier(d, gen, none);
+  if (blockIdx.x == 0) ph_units(d, epu);
   ph_masks(d, rl2);
-  grid_barrier(d, gen);
+  grid_barrier(d, gen, none);
   ph_end(d);
 }
 
@@ -600,19 +700,18 @@ hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, do
     hipLaunchKernelGGL(k_list_fused, dim3(fused_blocks), B, 0, st, d, pos, rlm, rl2, epu);
     return hipGetLastError();
   }
-  const int g_atoms = clampi((d.n_atoms + kBlk - 1) / kBlk, 1, 512);
-  const int g_cols = clampi(d.n_cols, 1, 512);
-  const int g_sc = clampi((d.sc_cap + 3) / 4, 1, 512);
-  const int g_ent = clampi(((long long)d.ent_cap + 3) / 4, 1, 512);
-  hipLaunchKernelGGL(k_begin, dim3(clampi((d.n_cols + kBlk - 1) / kBlk, 1, 64)), B, 0, st, d);
+  const int g_atoms = clampi((d.n_atoms + kBlk - 1) / kBlk, 1, 256);
+  const int g_sc = clampi((d.sc_cap + kWpb - 1) / kWpb, 1, 256);
+  const int g_srch = clampi((d.sc_cap * kStrips + kWpb - 1) / kWpb, 1, 512);
+  const int g_ent = clampi(((long long)d.ent_cap + kWpb - 1) / kWpb, 1, 256);
   hipLaunchKernelGGL(k_bin, dim3(g_atoms), B, 0, st, d, pos);
   hipLaunchKernelGGL(k_scan_cols, dim3(1), B, 0, st, d);
   hipLaunchKernelGGL(k_scatter, dim3(g_atoms), B, 0, st, d);
-  hipLaunchKernelGGL(k_sort_cols, dim3(g_cols), B, 0, st, d);
+  hipLaunchKernelGGL(k_sort_cols, dim3(g_sc), B, 0, st, d);
   hipLaunchKernelGGL(k_build_sc, dim3(g_sc), B, 0, st, d);
-  hipLaunchKernelGGL(k_search_count, dim3(g_sc), B, 0, st, d, rlm);
+  hipLaunchKernelGGL(k_search_count, dim3(g_srch), B, 0, st, d, rlm);
   hipLaunchKernelGGL(k_scan_entries, dim3(1), B, 0, st, d);
-  hipLaunchKernelGGL(k_search_write, dim3(g_sc), B, 0, st, d, rlm);
+  hipLaunchKernelGGL(k_search_write, dim3(g_srch), B, 0, st, d, rlm);
   hipLaunchKernelGGL(k_units, dim3(1), B, 0, st, d, epu, 0);
   hipLaunchKernelGGL(k_masks, dim3(g_ent), B, 0, st, d, rl2);
   hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, st, d);
@@ -643,6 +742,7 @@ __global__ void __launch_bounds__(kBlk) k_export(Dev d, double rl2, int* __restr
   const int lane = threadIdx.x & 63;
   const int il = lane & 7, jl = lane >> 3;
   const int n_ent = d.ctr[CTR_NENT];
+  int tiles = 0;  // 64-lane pair tiles of this wave's entries
   for (int e = gwave(); e < n_ent; e += gwaves()) {
     const int s = d.ent_isc[e];
     const int jc = d.ent_jc[e];

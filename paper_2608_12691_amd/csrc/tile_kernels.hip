@@ -551,7 +551,9 @@ __global__ void __launch_bounds__(kBlk) k_prepare(Dev d, const double* __restric
   }
   if (t == 0) {
     if (mode == 2) __atomic_store_n(d.rebuild, 1, __ATOMIC_RELAXED);
-    d.barrier[0] = 0u;  // arrival counter of the list build's grid barrier (clean after any timeout)
+    // arrival counters of the list build's grid barrier (clean after any timeout)
+    d.barrier[0] = 0u;
+    for (int g = 1; g <= kBarGroups; ++g) d.barrier[kBarStride * g] = 0u;
   }
   const bool have_list = d.ctr[CTR_NBUILD] > 0;
   bool moved = false, bad = false;
