@@ -66,12 +66,14 @@ def run_path(ctx, traj, lams, W, K, torch, graph):
         ctx.capture_step(pos, lam, out)
 
     def step(t):
-        pos.copy_(traj[t])
-        lam.copy_(lams[t])
         if graph:
+            # the captured graph reads fixed buffers: the step's inputs are copied in
+            pos.copy_(traj[t])
+            lam.copy_(lams[t])
             ctx.launch_step()
         else:
-            ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
+            # eager calls read the step's inputs where they already sit in HBM
+            ctx.compute(traj[t], lams[t], flags=alchnb.AUTO_REBUILD, out=out)
 
     for t in range(W):
         step(t)
@@ -223,6 +225,10 @@ def main():
                 "kernel": "k_tile<float, Beutler, switch>", "avg_launch_us": r32["tile_ms"] * 1e3,
                 "flop_per_pair": fpp, "pairs_per_launch": pairs_per_call,
                 "tiles_per_launch": r32["stats"]["n_tiles"],
+                "entries_per_launch": r32["stats"]["n_entries"],
+                "units_per_launch": r32["stats"]["n_units"],
+                "entries_per_unit": r32["stats"]["entries_per_unit"],
+                "blocks": r32["stats"]["blocks"],
                 "pair_slot_efficiency": pairs_per_call / (64.0 * r32["stats"]["n_tiles"]) if r32["stats"]["n_tiles"] else None}
     line = {
         "metric": "soft-core nonbonded pair-evals/s incl. forces+dU/dlambda; FP32-fixed vs FP64 GPU",

@@ -26,14 +26,20 @@ using namespace anb;
 namespace {
 
 struct Variant {
-  int epu, blocks, xcd;
+  int epu, tiles, ecost, blocks, part;  // entries and tiles per unit at most, entry cost, blocks, partition
 };
 // Launch variants of the tile kernel searched by alch_nb_autotune().
-const Variant kVariants[] = {
-    {8, 1024, 1}, {4, 2048, 1}, {16, 1024, 1}, {32, 512, 1}, {8, 1024, 0}, {8, 2048, 1}, {16, 2048, 1}, {2, 2048, 1},
+constexpr Variant kVariants[] = {
+    {8, 16, 0, 1024, 0}, {8, 16, 2, 1024, 1}, {8, 16, 2, 1024, 2}, {8, 16, 4, 1024, 2},
+    {8, 64, 0, 1024, 0}, {8, 16, 8, 1024, 2}, {8, 24, 4, 1024, 2}, {8, 12, 4, 1024, 2},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
-constexpr int kMinEpu = 2;
+constexpr bool variants_fit() {
+  for (const Variant& v : kVariants)
+    if (v.epu < 1 || v.epu > kMaxEpu) return false;
+  return true;
+}
+static_assert(variants_fit(), "the tile kernel stages the j-forces of at most kMaxEpu entries per unit");
 constexpr int kTimingSlots = 4096;
 
 struct Carve {
@@ -146,6 +152,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->atom_slot = cv.take<int>(base, N);
   d->slot_xw = cv.take<double4>(base, SL);
   d->slot_comp = cv.take<int>(base, SL);
+  d->slot_type = cv.take<int>(base, SL);
   d->se32 = cv.take<float2>(base, SL);
   d->se64 = cv.take<double2>(base, SL);
   d->q32 = cv.take<float>(base, SL);
@@ -165,10 +172,14 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->flags = cv.take<unsigned int>(base, 1);
   d->rebuild = cv.take<int>(base, 1);
   d->barrier = cv.take<unsigned int>(base, kBarWords);
+  d->unit_cost = cv.take<int>(base, U);
+  d->wave_ustart = cv.take<int>(base, kMaxWaves + 1);
   d->pos32 = cv.take<float4>(base, SL);
   d->pos64 = cv.take<double4>(base, SL);
   d->ffix = cv.take<unsigned long long>(base, 3 * SL);
   d->unit_acc = cv.take<double>(base, U * NACC);
+  d->chunk_acc = cv.take<double>(base, K * kRedChunks * NACC);
+  d->red_done = cv.take<unsigned int>(base, K);
   d->lam = cv.take<LamState>(base, K);
   d->last_dudl = cv.take<double>(base, K);
   d->pgrad_part = cv.take<double>(base, (size_t)kPgBlocks * 3 * ctx->T);
@@ -419,7 +430,7 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
     return ALCH_NB_E_UNSUPPORTED;
   }
   ctx->ent_cap = (int)ent_cap;
-  ctx->unit_cap = ctx->ent_cap / kMinEpu + ctx->sc_cap + 1;
+  ctx->unit_cap = ctx->ent_cap + ctx->sc_cap + 1;  // a unit holds at least one entry
 
   // potential constants (FP64)
   PotConsts& pc = ctx->pc;
@@ -524,10 +535,12 @@ static TileShape shape_of(const alch_nb_ctx* ctx) {
   const Variant& v = kVariants[ctx->variant];
   TileShape s;
   s.epu = v.epu;
-  s.xcd = v.xcd;
+  s.tiles = v.tiles;
+  s.ecost = v.ecost;
+  s.part = v.part;
   const long long need = ((long long)ctx->unit_cap + 3) / 4;
   long long b = std::min<long long>(v.blocks, std::max<long long>(8, need));
-  b = (b + 7) / 8 * 8;
+  b = std::min<long long>((b + 7) / 8 * 8, kMaxWaves / 4);
   s.blocks = (int)b;
   return s;
 }
@@ -542,7 +555,7 @@ static alch_nb_status enqueue_compute(alch_nb_ctx* ctx, const double* pos, const
   const Dev& d = ctx->dev;
   hipStream_t st = ctx->stream;
   HIPCHK(launch_prepare(d, st, pos, lam, mode, 0.5 * p.skin, p.schedule));
-  HIPCHK(launch_list_build(d, st, pos, ctx->r_list, sh.epu, ctx->fused_blocks));
+  HIPCHK(launch_list_build(d, st, pos, ctx->r_list, sh, ctx->fused_blocks));
   HIPCHK(launch_canon(d, st, pos, p.precision));
   const bool timed = allow_timing && ctx->timing && ctx->n_timed < kTimingSlots;
   if (timed) HIPCHK(hipEventRecord(ctx->ev[2 * ctx->n_timed], st));
@@ -570,16 +583,15 @@ alch_nb_status alch_nb_build_list(alch_nb_ctx* ctx, const double* d_pos) {
   if (!d_pos) return ALCH_NB_E_INVALID_ARG;
   const Dev& d = ctx->dev;
   HIPCHK(launch_prepare(d, ctx->stream, d_pos, nullptr, 2, 0.5 * ctx->p.skin, ctx->p.schedule));
-  HIPCHK(launch_list_build(d, ctx->stream, d_pos, ctx->r_list, shape_of(ctx).epu, ctx->fused_blocks));
+  HIPCHK(launch_list_build(d, ctx->stream, d_pos, ctx->r_list, shape_of(ctx), ctx->fused_blocks));
   return ALCH_NB_OK;
 }
 
 alch_nb_status alch_nb_set_variant(alch_nb_ctx* ctx, int32_t variant) {
   if (!ctx || variant < 0 || variant >= kNumVariants) return ALCH_NB_E_INVALID_ARG;
-  const int old_epu = kVariants[ctx->variant].epu;
   ctx->variant = variant;
   destroy_graph(ctx);
-  if (ctx->bound && kVariants[variant].epu != old_epu) HIPCHK(launch_units(ctx->dev, ctx->stream, kVariants[variant].epu));
+  if (ctx->bound) HIPCHK(launch_units(ctx->dev, ctx->stream, shape_of(ctx)));  // units and partition of this shape
   return ALCH_NB_OK;
 }
 

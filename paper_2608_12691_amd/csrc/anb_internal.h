@@ -24,6 +24,11 @@ constexpr int kSc = 64;          // atom slots per super-cluster
 constexpr int kBarGroups = 8;
 constexpr int kBarStride = 16;  // counters on separate 64-byte lines
 constexpr int kBarWords = kBarStride * (kBarGroups + 1);
+// work partition of the tile kernel: at most kMaxWaves waves per launch
+constexpr int kMaxWaves = 8192;
+constexpr int kUnitOverhead = 2;  // per-unit cost, in 64-pair tiles, of the partition
+constexpr int kRedChunks = 16;   // unit chunks per box in the final reduction
+constexpr int kAlchTileCost = 8;  // cost of a solute-solvent tile, in plain tiles
 constexpr int kStrips = 8;       // search waves per super-cluster (neighbour columns dealt round-robin)
 constexpr double kKe = 332.06371;
 constexpr int kNTerms = 10;  // energy-term slots per box
@@ -104,6 +109,7 @@ struct Dev {
   int* atom_slot;            // [N]
   double4* slot_xw;          // [SC*64] build-time wrapped position of the slot's atom
   int* slot_comp;            // [SC*64] exclusion component of the slot's atom (-1 = padding)
+  int* slot_type;            // [SC*64] atom type of the slot (0 for padding)
   float2* se32;              // [SC*64] sigma/2, 2 sqrt(eps)
   double2* se64;             // [SC*64]
   float* q32;                // [SC*64] q sqrt(k_e)
@@ -123,11 +129,15 @@ struct Dev {
   unsigned int* flags;       // [1] sticky flags
   int* rebuild;              // [1]
   unsigned int* barrier;     // [kBarWords] grid barrier: top count, generation, group counts
+  int* unit_cost;            // [U] tiles + overhead, then its exclusive prefix
+  int* wave_ustart;          // [kMaxWaves+1] first unit of each wave of the tile launch
   // per call
   float4* pos32;             // [SC*64] local x, y, z, q
   double4* pos64;            // [SC*64]
   unsigned long long* ffix;  // [3*SC*64] fixed-point forces, component-major
-  double* unit_acc;          // [U*NACC]
+  double* unit_acc;          // [NACC][U] per-unit partial sums (component-major)
+  double* chunk_acc;         // [K][kRedChunks][NACC] partial sums of unit chunks
+  unsigned int* red_done;    // [K] chunks reduced (the last one finishes its box; reset to 0)
   LamState* lam;             // [K]
   double* last_dudl;         // [K] dU/dlambda of the last forward
   double* pgrad_part;        // [PG_BLOCKS*3*T] parameter-gradient partials
@@ -135,7 +145,7 @@ struct Dev {
   const double4* tp64;       // [T*T]
 };
 
-enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6 };
+enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6, CTR_PART_W = 7 };
 
 constexpr int kPgBlocks = 512;  // blocks of the parameter-gradient pass
 constexpr int kMaxTypes = 256;  // atom types supported by the parameter-gradient pass

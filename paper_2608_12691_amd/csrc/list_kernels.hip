@@ -296,6 +296,7 @@ __device__ void ph_build_sc(const Dev& d) {
     d.slot_atom[sl] = a;
     d.slot_xw[sl] = make_double4(w[0], w[1], w[2], 0.0);
     d.slot_comp[sl] = a >= 0 ? d.atom_comp[a] : -1;
+    d.slot_type[sl] = a >= 0 ? d.atom_type[a] : 0;
     if (a >= 0) {
       d.atom_slot[a] = sl;
       const int t = d.atom_type[a];
@@ -479,30 +480,74 @@ __device__ void ph_scan_entries(const Dev& d) {
   __syncthreads();
 }
 
-// One block: work units of at most epu entries per SC, replica ranges.
-__device__ void ph_units(const Dev& d, int epu) {
+// One block, after the mask pass: work units, replica ranges and the
+// partition of the units over the W waves of a tile launch.  A unit is a run
+// of one SC's entries, cut greedily where it would exceed epu entries or,
+// past its first entry, tcap tiles (the tile counts are the pruned masks').
+// The waves take contiguous runs of units of about equal cost (tiles plus a
+// per-entry and per-unit overheads): unit u goes to wave floor(P_u W / P) for the exclusive
+// cost prefix P_u and total P, so the runs follow the unit order.
+// Tiles of an entry as counted by the unit cuts and the partition: a
+// solute-solvent tile takes its inputs from FP64 data and its pair
+// parameters from the type-pair table, about kAlchTileCost plain tiles.
+__device__ inline int entry_cost_tiles(uint32_t info) {
+  const int t = __popc(info & 0xffu);
+  return ((info >> 8) & 3u) == KIND_ALCH ? kAlchTileCost * t : t;
+}
+
+__device__ void ph_units(const Dev& d, int epu, int tcap, int ecost, int W) {
   const bool ok_all = d.ctr[CTR_NENT] == d.ctr[CTR_ENT_NEED];
   const int n = d.sc_cap;
-  for (int s = threadIdx.x; s < n; s += blockDim.x) d.sc_ustart[s] = ok_all ? (d.sc_ecount[s] + epu - 1) / epu : 0;
+  for (int s = threadIdx.x; s < n; s += blockDim.x) {
+    const int cnt = ok_all ? d.sc_ecount[s] : 0;
+    const int e0 = d.sc_estart[s];
+    int nu = 0, ne = 0, nt = 0;
+    for (int e = e0; e < e0 + cnt; ++e) {
+      const int t = entry_cost_tiles(d.ent_info[e]);
+      if (ne == 0 || ne == epu || nt + t > tcap) {
+        ++nu;
+        ne = 0;
+        nt = 0;
+      }
+      ++ne;
+      nt += t;
+    }
+    d.sc_ustart[s] = nu;
+  }
   __syncthreads();
   const int total = block_scan_array(d.sc_ustart, d.sc_ustart, n);
   const bool fits = total <= d.unit_cap;
   if (threadIdx.x == 0) {
     d.ctr[CTR_UNIT_NEED] = total;
     d.ctr[CTR_NUNIT] = fits ? total : 0;
+    d.ctr[CTR_PART_W] = W;
     if (!fits) atomicOr(d.flags, 16u);
   }
+  const int nu_all = fits ? total : 0;
   if (fits) {
     for (int s = threadIdx.x; s < n; s += blockDim.x) {
       const int cnt = ok_all ? d.sc_ecount[s] : 0;
       if (cnt == 0) continue;
-      const int u0 = d.sc_ustart[s];
       const int e0 = d.sc_estart[s];
       const int rep = d.grids[d.col_grid[d.sc_col[s]]].replica;
-      for (int u = 0; u * epu < cnt; ++u) {
-        const int b0 = e0 + u * epu;
-        d.units[u0 + u] = make_int4(s, b0, min(e0 + cnt, b0 + epu), rep);
+      int u = d.sc_ustart[s] - 1, ne = 0, nt = 0, b0 = e0;
+      for (int e = e0; e < e0 + cnt; ++e) {
+        const int t = entry_cost_tiles(d.ent_info[e]);
+        if (ne == 0 || ne == epu || nt + t > tcap) {
+          if (ne > 0) {
+            d.units[u] = make_int4(s, b0, e, rep);
+            d.unit_cost[u] = nt + ecost * ne + kUnitOverhead;
+          }
+          ++u;
+          ne = 0;
+          nt = 0;
+          b0 = e;
+        }
+        ++ne;
+        nt += t;
       }
+      d.units[u] = make_int4(s, b0, e0 + cnt, rep);
+      d.unit_cost[u] = nt + ecost * ne + kUnitOverhead;
     }
   }
   __syncthreads();
@@ -512,6 +557,19 @@ __device__ void ph_units(const Dev& d, int epu) {
     else if (k == d.n_reps) v = total;
     else v = d.reps[k].sc_begin < n ? d.sc_ustart[d.reps[k].sc_begin] : total;
     d.rep_ustart[k] = v;
+  }
+  // cost partition over the waves
+  const int ptot = block_scan_array(d.unit_cost, d.unit_cost, nu_all);
+  if (nu_all == 0) {
+    for (int w = threadIdx.x; w <= W; w += blockDim.x) d.wave_ustart[w] = 0;
+  } else {
+    for (int u = threadIdx.x; u < nu_all; u += blockDim.x) {
+      const int wu = (int)((long long)d.unit_cost[u] * W / ptot);
+      const int wp = u == 0 ? -1 : (int)((long long)d.unit_cost[u - 1] * W / ptot);
+      for (int w = wp + 1; w <= wu; ++w) d.wave_ustart[w] = u;
+      if (u == nu_all - 1)
+        for (int w = wu + 1; w <= W; ++w) d.wave_ustart[w] = nu_all;
+    }
   }
   __syncthreads();
 }
@@ -601,9 +659,9 @@ __global__ void __launch_bounds__(kBlk) k_build_sc(Dev d) { GATED; ph_build_sc(d
 __global__ void __launch_bounds__(kBlk) k_search_count(Dev d, double rlm) { GATED; ph_search<false>(d, rlm); }
 __global__ void __launch_bounds__(kBlk) k_scan_entries(Dev d) { GATED; ph_scan_entries(d); }
 __global__ void __launch_bounds__(kBlk) k_search_write(Dev d, double rlm) { GATED; ph_search<true>(d, rlm); }
-__global__ void __launch_bounds__(kBlk) k_units(Dev d, int epu, int force) {
+__global__ void __launch_bounds__(kBlk) k_units(Dev d, int epu, int tcap, int ecost, int waves, int force) {
   if (!force) { GATED; }
-  ph_units(d, epu);
+  ph_units(d, epu, tcap, ecost, waves);
 }
 __global__ void __launch_bounds__(kBlk) k_masks(Dev d, double rl2) { GATED; ph_masks(d, rl2); }
 __global__ void __launch_bounds__(kBlk) k_end(Dev d) { GATED; ph_end(d); }
@@ -666,7 +724,7 @@ __device__ inline void grid_barrier(const Dev& d, unsigned int& gen, Serial seri
 // The whole list build in one launch (phases separated by grid barriers;
 // the one-block scans run inside the barriers).
 __global__ void __launch_bounds__(kBlk) k_list_fused(Dev d, const double* __restrict__ pos, double rlm, double rl2,
-                                                     int epu) {
+                                                     int epu, int tcap, int ecost, int waves) {
   if (!rebuild_on(d)) return;
   __shared__ unsigned int gen_s;
   if (threadIdx.x == 0) gen_s = __hip_atomic_load(&d.barrier[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -685,19 +743,19 @@ __global__ void __launch_bounds__(kBlk) k_list_fused(Dev d, const double* __rest
   grid_barrier(d, gen, [&] { ph_scan_entries(d); });
   ph_search<true>(d, rlm);
   grid_barrier(d, gen, none);
-  if (blockIdx.x == 0) ph_units(d, epu);
   ph_masks(d, rl2);
-  grid_barrier(d, gen, none);
+  grid_barrier(d, gen, [&] { ph_units(d, epu, tcap, ecost, waves); });
   ph_end(d);
 }
 
-hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, double r_list, int epu,
+hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, double r_list, const TileShape& sh,
                              int fused_blocks) {
+  const int epu = sh.epu, tcap = sh.tiles, ecost = sh.ecost, waves = sh.blocks * 4;
   const double rlm = r_list * (1.0 + 1e-12) + 1e-9;  // conservative box test
   const double rl2 = rlm * rlm;  // masks keep the same margin; the export test is exact
   const dim3 B(kBlk);
   if (fused_blocks > 0) {
-    hipLaunchKernelGGL(k_list_fused, dim3(fused_blocks), B, 0, st, d, pos, rlm, rl2, epu);
+    hipLaunchKernelGGL(k_list_fused, dim3(fused_blocks), B, 0, st, d, pos, rlm, rl2, epu, tcap, ecost, waves);
     return hipGetLastError();
   }
   const int g_atoms = clampi((d.n_atoms + kBlk - 1) / kBlk, 1, 256);
@@ -712,8 +770,8 @@ hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, do
   hipLaunchKernelGGL(k_search_count, dim3(g_srch), B, 0, st, d, rlm);
   hipLaunchKernelGGL(k_scan_entries, dim3(1), B, 0, st, d);
   hipLaunchKernelGGL(k_search_write, dim3(g_srch), B, 0, st, d, rlm);
-  hipLaunchKernelGGL(k_units, dim3(1), B, 0, st, d, epu, 0);
   hipLaunchKernelGGL(k_masks, dim3(g_ent), B, 0, st, d, rl2);
+  hipLaunchKernelGGL(k_units, dim3(1), B, 0, st, d, epu, tcap, ecost, waves, 0);
   hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, st, d);
   return hipGetLastError();
 }
@@ -726,8 +784,8 @@ int list_fused_max_blocks() {
   return per_cu;
 }
 
-hipError_t launch_units(const Dev& d, hipStream_t st, int epu) {
-  hipLaunchKernelGGL(k_units, dim3(1), dim3(kBlk), 0, st, d, epu, 1);
+hipError_t launch_units(const Dev& d, hipStream_t st, const TileShape& sh) {
+  hipLaunchKernelGGL(k_units, dim3(1), dim3(kBlk), 0, st, d, sh.epu, sh.tiles, sh.ecost, sh.blocks * 4, 1);
   return hipGetLastError();
 }
 

@@ -9,8 +9,10 @@
 //   j-cluster (8 atoms, each read by 8 lanes) and loops over the i-clusters
 //   its mask selects, so one pass covers up to 8 x 64 atom pairs.
 //   j-forces are summed over the 8 i-clusters in registers and then over il
-//   with DPP lane moves, and leave with one 64-bit fixed-point atomic per
-//   component and j-atom; i-forces stay in registers until the unit ends.
+//   with DPP lane moves and parked in LDS; i-forces stay in registers.  At
+//   the end of the unit both leave as 64-bit fixed-point atomics with one
+//   atom per lane (three 64-lane atomics each), so the entry loop issues no
+//   memory writes and never waits for one.
 // Pair arithmetic is FP32 (or FP64 in the reference path); positions are
 // super-cluster-local so that FP32 keeps ~1e-7 A resolution in any box.
 #include <hip/hip_runtime.h>
@@ -179,15 +181,16 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+
+// Fixed-point add of one value per active lane with no per-lane branch
+// around the atomic; out-of-range or NaN values add zero and raise the
+// overflow flag.
 template <typename R>
-__device__ inline void add_fixed(unsigned long long* p, R v, double scale, unsigned int* flags) {
-  if (v == R(0)) return;
+__device__ inline void add_fixed_lanes(unsigned long long* p, R v, double scale, unsigned int* flags, bool active) {
   const double x = (double)v * scale;
-  if (!(fabs(x) < 4.611686018427388e18)) {  // |f| >= 2^62 / scale, or NaN
-    atomicOr(flags, 1u);
-    return;
-  }
-  atomicAdd(p, (unsigned long long)__double2ll_rn(x));
+  const bool ok = fabs(x) < 4.611686018427388e18;  // |f| < 2^62 / scale
+  if (__ballot(active && !ok) && (threadIdx.x & 63) == 0) atomicOr(flags, 1u);
+  if (active) atomicAdd(p, ok ? (unsigned long long)__double2ll_rn(x) : 0ull);
 }
 
 // ------------------------------------------------------------ tile kernel
@@ -263,41 +266,84 @@ __device__ inline void alch_pair(R dx, R dy, R dz, bool valid, const typename C4
 }
 
 template <typename R, int SCHED, bool SW>
-__global__ void __launch_bounds__(kBlk) k_tile(Dev d, Pot<R> P, int xcd, double fscale, const double* __restrict__ xin) {
+__global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Pot<R> P, int part, double fscale, const double* __restrict__ xin) {
   using P4 = typename C4<R>::P4;
   using P2 = typename C4<R>::P2;
   const P4* __restrict__ pos = reinterpret_cast<const P4*>(sizeof(R) == 4 ? (const void*)d.pos32 : (const void*)d.pos64);
   const P2* __restrict__ se = reinterpret_cast<const P2*>(sizeof(R) == 4 ? (const void*)d.se32 : (const void*)d.se64);
   const P4* __restrict__ tpair = reinterpret_cast<const P4*>(sizeof(R) == 4 ? (const void*)d.tp32 : (const void*)d.tp64);
+  const double4* __restrict__ pos64 = d.pos64;
   const int slots = d.sc_cap * kSc;
   const int T = d.n_types;
   const int lane = threadIdx.x & 63;
   __shared__ P4 ipos_all[kBlk];
   __shared__ P2 ise_all[kBlk];
+  // j-forces of up to 8 entries (entry slot k, j-atom jl at k * 8 + jl)
+  __shared__ P4 jf_all[kBlk];
+  __shared__ int jsl_all[kBlk];
+  P4* jf = jf_all + (threadIdx.x & ~63);
+  int* jslb = jsl_all + (threadIdx.x & ~63);
+  // j-cluster data of the unit's entries (same layout), positions already
+  // moved into the i-super-cluster's frame and entry image
+  __shared__ P4 jpos_all[kBlk];
+  __shared__ P2 jse_all[kBlk];
+  P4* jpos = jpos_all + (threadIdx.x & ~63);
+  P2* jse = jse_all + (threadIdx.x & ~63);
+  // lane-private FP64 sums of the rare entry kinds (solute-solute and
+  // solute-solvent) live in LDS, keeping registers for the common path
+  __shared__ double rare_all[4][kBlk];
+  double* rare0 = &rare_all[0][threadIdx.x];  // solute-solute energy
+  double* rare1 = &rare_all[1][threadIdx.x];  // a0 .. a2 of the alchemical pairs
+  double* rare2 = &rare_all[2][threadIdx.x];
+  double* rare3 = &rare_all[3][threadIdx.x];
   P4* ipos = ipos_all + (threadIdx.x & ~63);
   P2* ise = ise_all + (threadIdx.x & ~63);
   const int il = lane & 7, jl = lane >> 3;
   const int n_units = d.ctr[CTR_NUNIT];
-  // Unit range of this wave.  XCD-aware: blocks are dispatched round-robin
-  // over the 8 XCDs, so XCD x (blocks b with b % 8 == x) takes the x-th
-  // contiguous eighth of the units (neighbouring super-clusters share
-  // j-clusters, which then stay in that XCD's L2) and splits it evenly
-  // over its waves.  Otherwise consecutive waves take consecutive runs.
-  // wave index made provably uniform: unit and entry indices then live in
-  // scalar registers and their loads are scalar loads
+  // Unit range of this wave.  Blocks are dispatched round-robin over the 8
+  // XCDs; with xcd set, XCD x (blocks b with b % 8 == x) takes the x-th
+  // eighth of the waves' runs of the list-build partition (runs of about
+  // equal cost, neighbouring super-clusters kept together, so shared
+  // j-clusters stay in that XCD's L2).  Otherwise, or when the partition
+  // was made for another launch shape, waves take equal runs of units.
+  // The wave index is made provably uniform: unit and entry indices then
+  // live in scalar registers and their loads are scalar loads.
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nw = gridDim.x * (kBlk / 64);
   int ub, ue;
-  if (xcd && (gridDim.x & 7) == 0) {
-    const int x = blockIdx.x & 7, nbx = gridDim.x >> 3, lb = blockIdx.x >> 3;
-    const int c0 = (int)((long long)n_units * x / 8), c1 = (int)((long long)n_units * (x + 1) / 8);
-    const int nwx = nbx * (kBlk / 64), w = lb * (kBlk / 64) + wib;
-    ub = c0 + (int)((long long)(c1 - c0) * w / nwx);
-    ue = c0 + (int)((long long)(c1 - c0) * (w + 1) / nwx);
+  if (part && (gridDim.x & 7) == 0 && as_const(d.ctr)[CTR_PART_W] == nw) {
+    const int r = part == 1 ? (blockIdx.x & 7) * (nw >> 3) + (blockIdx.x >> 3) * (kBlk / 64) + wib
+                            : blockIdx.x * (kBlk / 64) + wib;
+    const cptr<int> ws = as_const(d.wave_ustart);
+    ub = ws[r];
+    ue = ws[r + 1];
   } else {
-    const int nw = gridDim.x * (kBlk / 64), w = blockIdx.x * (kBlk / 64) + wib;
+    const int w = blockIdx.x * (kBlk / 64) + wib;
     ub = (int)((long long)n_units * w / nw);
     ue = (int)((long long)n_units * (w + 1) / nw);
   }
+  // i-forces of the current super-cluster, carried over consecutive units
+  // of the same super-cluster; they leave when it changes: summed over jl,
+  // lane (jl, il) then takes i-cluster c = jl so that lane l holds slot
+  // s * 64 + l, and three 64-lane atomics write them
+  R fix[kScCl], fiy[kScCl], fiz[kScCl];
+  int cur_s = -1;
+  auto flush_i = [&](int sc) {
+    R gx = R(0), gy = R(0), gz = R(0);
+#pragma unroll
+    for (int c = 0; c < kScCl; ++c) {
+      const R fx = red_jl(fix[c]), fy = red_jl(fiy[c]), fz = red_jl(fiz[c]);
+      if (jl == c) {
+        gx = fx;
+        gy = fy;
+        gz = fz;
+      }
+    }
+    const int sl = sc * kSc + lane;
+    add_fixed_lanes(d.ffix + sl, gx, fscale, d.flags, true);
+    add_fixed_lanes(d.ffix + slots + sl, gy, fscale, d.flags, true);
+    add_fixed_lanes(d.ffix + 2 * slots + sl, gz, fscale, d.flags, true);
+  };
   for (int u = ub; u < ue; ++u) {
     const cptr<int> up = as_const(reinterpret_cast<const int*>(d.units)) + 4 * u;
     const int4 U = make_int4(up[0], up[1], up[2], up[3]);
@@ -313,33 +359,57 @@ __global__ void __launch_bounds__(kBlk) k_tile(Dev d, Pot<R> P, int xcd, double 
       la0 = (R)lam.a[0];
       la1 = (R)lam.a[1];
     }
-    // the super-cluster's 64 atoms go to this wave's LDS slice (lane l holds
-    // slot l); lane (jl, il) then reads atom c*8 + il for each i-cluster c
-    R fix[kScCl], fiy[kScCl], fiz[kScCl];
-    wave_sync();
-    ipos[lane] = pos[s * kSc + lane];
-    ise[lane] = se[s * kSc + lane];
-    wave_sync();
+    if (s != cur_s) {
+      if (cur_s >= 0) flush_i(cur_s);
+      // the super-cluster's 64 atoms go to this wave's LDS slice (lane l
+      // holds slot l); lane (jl, il) then reads atom c*8 + il of i-cluster c
+      wave_sync();
+      ipos[lane] = pos[s * kSc + lane];
+      ise[lane] = se[s * kSc + lane];
+      wave_sync();
 #pragma unroll
-    for (int c = 0; c < kScCl; ++c) fix[c] = fiy[c] = fiz[c] = R(0);
+      for (int c = 0; c < kScCl; ++c) fix[c] = fiy[c] = fiz[c] = R(0);
+      cur_s = s;
+    }
     const double ox0 = as_const(d.sc_origin)[3 * s], oy0 = as_const(d.sc_origin)[3 * s + 1],
                  oz0 = as_const(d.sc_origin)[3 * s + 2];
-    double acc_solv = 0, acc_solu = 0, acc_a0 = 0, acc_a1 = 0, acc_a2 = 0;
+    double acc_solv = 0;
+    bool rare = false;  // wave-uniform: the unit had a solute-solute or solute-solvent entry
+    *rare0 = *rare1 = *rare2 = *rare3 = 0.0;
     int npair = 0;
-    // software pipeline: entry words two ahead, j-cluster data one ahead
-    const cptr<int> ejc = as_const(d.ent_jc);
-    const cptr<uint32_t> einfo = as_const(d.ent_info);
-    const cptr<double> sorg = as_const(d.sc_origin);
-    int jc_a = ejc[U.y];
-    uint32_t info_a = einfo[U.y];
-    int jc_b = jc_a;
-    uint32_t info_b = info_a;
-    if (U.y + 1 < U.z) {
-      jc_b = ejc[U.y + 1];
-      info_b = einfo[U.y + 1];
+    // j-cluster data of all entries of the unit, one load per lane: lane
+    // (k, t) takes atom t of entry U.y + k (units hold at most 8 entries)
+    {
+      const int k = lane >> 3, t = lane & 7, e = U.y + k;
+      P4 v;
+      P2 q;
+      v.x = v.y = v.z = v.w = R(0);
+      q.x = q.y = R(0);
+      int jsl = 0;
+      if (e < U.z) {
+        const int jc = d.ent_jc[e];
+        const int code = (int)((d.ent_info[e] >> 16) & 31u);
+        const int sj = jc >> 3;
+        jsl = jc * kCl + t;
+        v = pos[jsl];
+        q = se[jsl];
+        // offset of the j-cluster's image from the i-super-cluster origin
+        const double odx = d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
+        const double ody = d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
+        const double odz = d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
+        v.x += (R)odx;
+        v.y += (R)ody;
+        v.z += (R)odz;
+      }
+      wave_sync();
+      jpos[lane] = v;
+      jse[lane] = q;
+      jslb[lane] = jsl;
+      wave_sync();
     }
-    P4 pj_a = pos[jc_a * kCl + jl];
-    P2 qj_a = se[jc_a * kCl + jl];
+    // entry words and pair masks one entry ahead (scalar loads)
+    const cptr<uint32_t> einfo = as_const(d.ent_info);
+    uint32_t info_a = einfo[U.y];
     const cptr<unsigned long long> emask = as_const(d.ent_mask);
     unsigned long long m_a[kScCl];
 #pragma unroll
@@ -348,46 +418,76 @@ __global__ void __launch_bounds__(kBlk) k_tile(Dev d, Pot<R> P, int xcd, double 
       unsigned long long mcur[kScCl];
 #pragma unroll
       for (int c = 0; c < kScCl; ++c) mcur[c] = m_a[c];
+      const uint32_t info = info_a;
       if (e + 1 < U.z) {
 #pragma unroll
         for (int c = 0; c < kScCl; ++c) m_a[c] = emask[(size_t)(e + 1) * kScCl + c];
+        info_a = einfo[e + 1];
       }
-      const int jc = jc_a;
-      const uint32_t info = info_a;
-      const P4 pj = pj_a;
-      const P2 qj = qj_a;
-      jc_a = jc_b;
-      info_a = info_b;
-      if (e + 1 < U.z) {
-        pj_a = pos[jc_a * kCl + jl];
-        qj_a = se[jc_a * kCl + jl];
-      }
-      if (e + 2 < U.z) {
-        jc_b = ejc[e + 2];
-        info_b = einfo[e + 2];
-      }
+      const int k = e - U.y;  // entry slot in this unit
       const uint32_t imask = info & 0xffu;
       const int kind = (int)((info >> 8) & 3u);
-      const int jsl = jc * kCl + jl;
+      const int jsl = jslb[k * kCl + jl];
       R fjx = R(0), fjy = R(0), fjz = R(0), eent = R(0);
-      // offset of the j-cluster's image from the i-super-cluster origin
-      const int code = (int)((info >> 16) & 31u);
-      const int sj = jc >> 3;
-      const double odx = sorg[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
-      const double ody = sorg[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
-      const double odz = sorg[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
-      if (kind != KIND_ALCH) {
-        const R xj = pj.x + (R)odx, yj = pj.y + (R)ody, zj = pj.z + (R)odz;
+      if (kind == KIND_ALCH) {
+        // FP64 local coordinates (written by the canon pass for every slot),
+        // moved into this entry's image and rounded once per displacement
+        const int code = (int)((info >> 16) & 31u);
+        const int sj = jsl >> 6;
+        const double odx = d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
+        const double ody = d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
+        const double odz = d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
+        const double4 pj64 = pos64[jsl];
+        const double xj = pj64.x + odx, yj = pj64.y + ody, zj = pj64.z + odz;
+        const int tj = d.slot_type[jsl];
+        double a0 = 0, a1 = 0, a2 = 0;
 #pragma unroll
         for (int c = 0; c < kScCl; ++c) {
           if (!(imask & (1u << c))) continue;
-          const bool valid = (mcur[c] >> lane) & 1ull;
-          const P4 pi = ipos[c * kCl + il];
-          const P2 qi = ise[c * kCl + il];
+          const int isl = s * kSc + c * kCl + il;
+          const double4 pi64 = pos64[isl];
+          const R dx = (R)(xj - pi64.x), dy = (R)(yj - pi64.y), dz = (R)(zj - pi64.z);
+          const P4 tp = tpair[d.slot_type[isl] * T + tj];
+          R u, fr, rinv2;
+          bool inr;
+          const bool valid = __builtin_amdgcn_inverse_ballot_w64(mcur[c]);
+          alch_pair<R, SCHED, SW>(dx, dy, dz, valid, tp, la0, la1, P, u, fr, rinv2, inr, a0, a1, a2);
+          npair += __popcll(__ballot(inr));
+          const R fs = inr ? fr * rinv2 : R(0);
+          const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
+          fjx += fx;
+          fjy += fy;
+          fjz += fz;
+          fix[c] -= fx;
+          fiy[c] -= fy;
+          fiz[c] -= fz;
+        }
+        *rare1 += a0;
+        *rare2 += a1;
+        *rare3 += a2;
+        rare = true;
+      } else {
+        const P4 pj = jpos[k * kCl + jl];
+        const P2 qj = jse[k * kCl + jl];
+        const R xj = pj.x, yj = pj.y, zj = pj.z;
+        // i-cluster data one cluster ahead (LDS reads are always in bounds)
+        P4 pin = ipos[il];
+        P2 qin = ise[il];
+#pragma unroll
+        for (int c = 0; c < kScCl; ++c) {
+          const P4 pi = pin;
+          const P2 qi = qin;
+          if (c + 1 < kScCl) {
+            pin = ipos[(c + 1) * kCl + il];
+            qin = ise[(c + 1) * kCl + il];
+          }
+          if (!(imask & (1u << c))) continue;
           const R dx = xj - pi.x, dy = yj - pi.y, dz = zj - pi.z;
           const R r2 = dx * dx + dy * dy + dz * dz;
-          const bool inr = valid && r2 < P.rc2;
-          npair += __popcll(__ballot(inr));
+          // the pair mask is a lane mask: combine it on the scalar unit
+          const unsigned long long inm = __ballot(r2 < P.rc2) & mcur[c];
+          npair += __popcll(inm);
+          const bool inr = __builtin_amdgcn_inverse_ballot_w64(inm);
           PairCore<R, SW> pc;
           pc.eval(r2, inr, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P);
           const R u = pc.lj0 * pc.S + pc.el;
@@ -402,72 +502,62 @@ __global__ void __launch_bounds__(kBlk) k_tile(Dev d, Pot<R> P, int xcd, double 
           fiy[c] -= fy;
           fiz[c] -= fz;
         }
-      } else {
-        // FP64 local coordinates from the input positions, in this entry's image
-        const int aj = max(0, d.slot_atom[jsl]);
-        const double xj = local_coord(d, xin, aj, sj, 0, L0) + odx;
-        const double yj = local_coord(d, xin, aj, sj, 1, L1) + ody;
-        const double zj = local_coord(d, xin, aj, sj, 2, L2) + odz;
-        const int tj = d.atom_type[aj];
-#pragma unroll
-        for (int c = 0; c < kScCl; ++c) {
-          if (!(imask & (1u << c))) continue;
-          const bool valid = (mcur[c] >> lane) & 1ull;
-          const int ai = max(0, d.slot_atom[s * kSc + c * kCl + il]);
-          const double xl = local_coord(d, xin, ai, s, 0, L0), yl = local_coord(d, xin, ai, s, 1, L1),
-                       zl = local_coord(d, xin, ai, s, 2, L2);
-          const R dx = (R)(xj - xl), dy = (R)(yj - yl), dz = (R)(zj - zl);
-          const P4 tp = tpair[d.atom_type[ai] * T + tj];
-          R u, fr, rinv2;
-          bool inr;
-          alch_pair<R, SCHED, SW>(dx, dy, dz, valid, tp, la0, la1, P, u, fr, rinv2, inr, acc_a0, acc_a1, acc_a2);
-          npair += __popcll(__ballot(inr));
-          const R fs = inr ? fr * rinv2 : R(0);
-          const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
-          fjx += fx;
-          fjy += fy;
-          fjz += fz;
-          fix[c] -= fx;
-          fiy[c] -= fy;
-          fiz[c] -= fz;
-        }
       }
       fjx = red8(fjx);
       fjy = red8(fjy);
       fjz = red8(fjz);
       if (il == 0) {
-        add_fixed(d.ffix + jsl, fjx, fscale, d.flags);
-        add_fixed(d.ffix + slots + jsl, fjy, fscale, d.flags);
-        add_fixed(d.ffix + 2 * slots + jsl, fjz, fscale, d.flags);
+        P4 v;
+        v.x = fjx;
+        v.y = fjy;
+        v.z = fjz;
+        v.w = R(0);
+        jf[k * kCl + jl] = v;
+        jslb[k * kCl + jl] = jsl;
       }
-      if (kind == KIND_SOLV) acc_solv += (double)eent;
-      else if (kind == KIND_SOLU) acc_solu += (double)eent;
-    }
-#pragma unroll
-    for (int c = 0; c < kScCl; ++c) {
-      const R fx = red_jl(fix[c]), fy = red_jl(fiy[c]), fz = red_jl(fiz[c]);
-      if (jl == 0) {
-        const int sl = s * kSc + c * kCl + il;
-        add_fixed(d.ffix + sl, fx, fscale, d.flags);
-        add_fixed(d.ffix + slots + sl, fy, fscale, d.flags);
-        add_fixed(d.ffix + 2 * slots + sl, fz, fscale, d.flags);
+      if (kind == KIND_SOLV) {
+        acc_solv += (double)eent;
+      } else if (kind == KIND_SOLU) {
+        *rare0 += (double)eent;
+        rare = true;
       }
     }
+    // j-forces parked by the entries of this unit
+    wave_sync();
+    {
+      const bool have = lane < (U.z - U.y) * kCl;
+      P4 v;
+      v.x = v.y = v.z = v.w = R(0);
+      int sl = 0;
+      if (have) {
+        v = jf[lane];
+        sl = jslb[lane];
+      }
+      add_fixed_lanes(d.ffix + sl, v.x, fscale, d.flags, have);
+      add_fixed_lanes(d.ffix + slots + sl, v.y, fscale, d.flags, have);
+      add_fixed_lanes(d.ffix + 2 * slots + sl, v.z, fscale, d.flags, have);
+    }
+    wave_sync();
     acc_solv = wave_sum(acc_solv);
-    acc_solu = wave_sum(acc_solu);
-    acc_a0 = wave_sum(acc_a0);
-    acc_a1 = wave_sum(acc_a1);
-    acc_a2 = wave_sum(acc_a2);
+    double acc_solu = 0, acc_a0 = 0, acc_a1 = 0, acc_a2 = 0;
+    if (rare) {
+      acc_solu = wave_sum(*rare0);
+      acc_a0 = wave_sum(*rare1);
+      acc_a1 = wave_sum(*rare2);
+      acc_a2 = wave_sum(*rare3);
+    }
     if (lane == 0) {
-      double* o = d.unit_acc + (size_t)u * NACC;
-      o[ACC_SOLV] = acc_solv;
-      o[ACC_SOLU] = acc_solu;
-      o[ACC_A0] = acc_a0;
-      o[ACC_A1] = acc_a1;
-      o[ACC_A2] = acc_a2;
-      o[ACC_NPAIR] = (double)npair;
+      const size_t U = (size_t)d.unit_cap;
+      double* o = d.unit_acc + u;
+      o[ACC_SOLV * U] = acc_solv;
+      o[ACC_SOLU * U] = acc_solu;
+      o[ACC_A0 * U] = acc_a0;
+      o[ACC_A1 * U] = acc_a1;
+      o[ACC_A2 * U] = acc_a2;
+      o[ACC_NPAIR * U] = (double)npair;
     }
   }
+  if (cur_s >= 0) flush_i(cur_s);
 }
 
 hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
@@ -478,20 +568,20 @@ hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int pr
   if (precision == 0) {
     const Pot<float> P = make_pot<float>(pc);
     if (schedule == 0) {
-      if (sw) hipLaunchKernelGGL((k_tile<float, 0, true>), G, B, 0, st, d, P, sh.xcd, fs, xin);
-      else hipLaunchKernelGGL((k_tile<float, 0, false>), G, B, 0, st, d, P, sh.xcd, fs, xin);
+      if (sw) hipLaunchKernelGGL((k_tile<float, 0, true>), G, B, 0, st, d, P, sh.part, fs, xin);
+      else hipLaunchKernelGGL((k_tile<float, 0, false>), G, B, 0, st, d, P, sh.part, fs, xin);
     } else {
-      if (sw) hipLaunchKernelGGL((k_tile<float, 1, true>), G, B, 0, st, d, P, sh.xcd, fs, xin);
-      else hipLaunchKernelGGL((k_tile<float, 1, false>), G, B, 0, st, d, P, sh.xcd, fs, xin);
+      if (sw) hipLaunchKernelGGL((k_tile<float, 1, true>), G, B, 0, st, d, P, sh.part, fs, xin);
+      else hipLaunchKernelGGL((k_tile<float, 1, false>), G, B, 0, st, d, P, sh.part, fs, xin);
     }
   } else {
     const Pot<double> P = make_pot<double>(pc);
     if (schedule == 0) {
-      if (sw) hipLaunchKernelGGL((k_tile<double, 0, true>), G, B, 0, st, d, P, sh.xcd, fs, xin);
-      else hipLaunchKernelGGL((k_tile<double, 0, false>), G, B, 0, st, d, P, sh.xcd, fs, xin);
+      if (sw) hipLaunchKernelGGL((k_tile<double, 0, true>), G, B, 0, st, d, P, sh.part, fs, xin);
+      else hipLaunchKernelGGL((k_tile<double, 0, false>), G, B, 0, st, d, P, sh.part, fs, xin);
     } else {
-      if (sw) hipLaunchKernelGGL((k_tile<double, 1, true>), G, B, 0, st, d, P, sh.xcd, fs, xin);
-      else hipLaunchKernelGGL((k_tile<double, 1, false>), G, B, 0, st, d, P, sh.xcd, fs, xin);
+      if (sw) hipLaunchKernelGGL((k_tile<double, 1, true>), G, B, 0, st, d, P, sh.part, fs, xin);
+      else hipLaunchKernelGGL((k_tile<double, 1, false>), G, B, 0, st, d, P, sh.part, fs, xin);
     }
   }
   return hipGetLastError();
@@ -602,11 +692,11 @@ __global__ void __launch_bounds__(kBlk) k_canon(Dev d, const double* __restrict_
     d.ffix[2 * slots + sl] = 0ull;
     const int a = d.slot_atom[sl];
     P4 v;
+    double q[3] = {0.0, 0.0, 0.0};
     if (a < 0) {
       v.x = v.y = v.z = v.w = R(0);
     } else {
       const ReplicaInfo& rp = d.reps[d.grids[d.atom_grid[a]].replica];
-      double q[3];
       for (int k = 0; k < 3; ++k) q[k] = local_coord(d, pos, a, s, k, rp.box[k]);
       v.x = (R)q[0];
       v.y = (R)q[1];
@@ -614,6 +704,9 @@ __global__ void __launch_bounds__(kBlk) k_canon(Dev d, const double* __restrict_
       v.w = sizeof(R) == 4 ? (R)d.q32[sl] : (R)d.q64[sl];
     }
     out[sl] = v;
+    // the FP32 path's solute-solvent pairs take their displacements from
+    // these FP64 coordinates
+    if (sizeof(R) == 4) d.pos64[sl] = make_double4(q[0], q[1], q[2], 0.0);
   }
 }
 
@@ -625,19 +718,27 @@ hipError_t launch_canon(const Dev& d, hipStream_t st, const double* pos, int pre
   return hipGetLastError();
 }
 
-// Blocks [0, K): ordered reduction of the unit partials of box k and the
-// energy terms.  Blocks >= K: fixed-point forces -> float64 in atom order.
+// Blocks [0, K * kRedChunks): block (k, c) sums chunk c of box k's unit
+// partials (fixed chunk bounds and tree order); the last chunk of box k to
+// finish (counter red_done[k]) adds the kRedChunks chunk sums in order and
+// writes the energy terms.  Blocks beyond: fixed-point forces -> float64 in
+// atom order.
 __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double inv_scale, double* __restrict__ terms,
                                                    double* __restrict__ forces, double* __restrict__ dudl,
                                                    long long* __restrict__ n_pairs) {
   __shared__ double red[NACC][kBlk];
+  __shared__ int last;
   const int K = d.n_reps;
-  if ((int)blockIdx.x < K) {
-    const int k = blockIdx.x;
+  const int nred = K * kRedChunks;
+  if ((int)blockIdx.x < nred) {
+    const int k = blockIdx.x / kRedChunks, c = blockIdx.x % kRedChunks;
     const int u0 = d.rep_ustart[k], u1 = d.rep_ustart[k + 1];
+    const int c0 = u0 + (int)((long long)(u1 - u0) * c / kRedChunks);
+    const int c1 = u0 + (int)((long long)(u1 - u0) * (c + 1) / kRedChunks);
+    const size_t U = (size_t)d.unit_cap;
     double s[NACC] = {0, 0, 0, 0, 0, 0};
-    for (int u = u0 + threadIdx.x; u < u1; u += blockDim.x)
-      for (int j = 0; j < NACC; ++j) s[j] += d.unit_acc[(size_t)u * NACC + j];
+    for (int u = c0 + threadIdx.x; u < c1; u += blockDim.x)
+      for (int j = 0; j < NACC; ++j) s[j] += d.unit_acc[j * U + u];
     for (int j = 0; j < NACC; ++j) red[j][threadIdx.x] = s[j];
     __syncthreads();
     for (int off = kBlk / 2; off > 0; off >>= 1) {
@@ -646,32 +747,42 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      const double solv = red[ACC_SOLV][0], solu = red[ACC_SOLU][0];
-      const double a0 = red[ACC_A0][0], a1 = red[ACC_A1][0], a2 = red[ACC_A2][0];
-      const LamState L = d.lam[k];
-      double t[kNTerms];
-      if (schedule == 0) {
-        // a0 = sum lv core S, a1 = sum qq D, a2 = sum d(lv core S)/dlv
-        t[0] = solv; t[1] = solu; t[2] = a0; t[3] = L.a[1] * a1; t[4] = 0.0; t[5] = 0.0;
-        t[6] = L.a[2] * a2; t[7] = L.a[3] * a1;
-      } else {
-        // a0 = sum LJ S, a1 = sum qq D, a2 = sum eps u_cap S
-        t[0] = solv; t[1] = solu; t[2] = L.a[0] * a0 + L.a[1] * a2; t[3] = L.a[0] * a1;
-        t[4] = a0 + a1; t[5] = a2; t[6] = L.a[2] * a0 + L.a[3] * a2; t[7] = L.a[2] * a1;
-      }
-      t[8] = ((t[0] + t[1]) + t[2]) + t[3];
-      t[9] = t[6] + t[7];
-      if (terms)
-        for (int j = 0; j < kNTerms; ++j) terms[k * kNTerms + j] = t[j];
-      if (dudl) dudl[k] = t[9];
-      d.last_dudl[k] = t[9];
-      if (n_pairs) n_pairs[k] = (long long)red[ACC_NPAIR][0];
+      for (int j = 0; j < NACC; ++j) d.chunk_acc[(size_t)blockIdx.x * NACC + j] = red[j][0];
+      // publish the chunk sums, then count; the last chunk acquires them all
+      last = __hip_atomic_fetch_add(&d.red_done[k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+             (unsigned int)(kRedChunks - 1);
     }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    d.red_done[k] = 0u;
+    double a[NACC] = {0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < kRedChunks; ++q)
+      for (int j = 0; j < NACC; ++j) a[j] += d.chunk_acc[((size_t)k * kRedChunks + q) * NACC + j];
+    const double solv = a[ACC_SOLV], solu = a[ACC_SOLU];
+    const double a0 = a[ACC_A0], a1 = a[ACC_A1], a2 = a[ACC_A2];
+    const LamState L = d.lam[k];
+    double t[kNTerms];
+    if (schedule == 0) {
+      // a0 = sum lv core S, a1 = sum qq D, a2 = sum d(lv core S)/dlv
+      t[0] = solv; t[1] = solu; t[2] = a0; t[3] = L.a[1] * a1; t[4] = 0.0; t[5] = 0.0;
+      t[6] = L.a[2] * a2; t[7] = L.a[3] * a1;
+    } else {
+      // a0 = sum LJ S, a1 = sum qq D, a2 = sum eps u_cap S
+      t[0] = solv; t[1] = solu; t[2] = L.a[0] * a0 + L.a[1] * a2; t[3] = L.a[0] * a1;
+      t[4] = a0 + a1; t[5] = a2; t[6] = L.a[2] * a0 + L.a[3] * a2; t[7] = L.a[2] * a1;
+    }
+    t[8] = ((t[0] + t[1]) + t[2]) + t[3];
+    t[9] = t[6] + t[7];
+    if (terms)
+      for (int j = 0; j < kNTerms; ++j) terms[k * kNTerms + j] = t[j];
+    if (dudl) dudl[k] = t[9];
+    d.last_dudl[k] = t[9];
+    if (n_pairs) n_pairs[k] = (long long)a[ACC_NPAIR];
     return;
   }
   if (!forces) return;
   const int slots = d.sc_cap * kSc;
-  for (int a = (blockIdx.x - K) * blockDim.x + threadIdx.x; a < d.n_atoms; a += (gridDim.x - K) * blockDim.x) {
+  for (int a = (blockIdx.x - nred) * blockDim.x + threadIdx.x; a < d.n_atoms; a += (gridDim.x - nred) * blockDim.x) {
     const int sl = d.atom_slot[a];
     for (int c = 0; c < 3; ++c) forces[3 * a + c] = (double)(long long)d.ffix[c * slots + sl] * inv_scale;
   }
@@ -680,7 +791,8 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
 hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int schedule, double* terms, double* forces,
                            double* dudl, long long* n_pairs) {
   const int gf = forces ? max(1, min(1024, (d.n_atoms + kBlk - 1) / kBlk)) : 0;
-  hipLaunchKernelGGL(k_finalize, dim3(d.n_reps + gf), dim3(kBlk), 0, st, d, schedule, 1.0 / fixed_scale(precision),
+  hipLaunchKernelGGL(k_finalize, dim3(d.n_reps * kRedChunks + gf), dim3(kBlk), 0, st, d, schedule,
+                     1.0 / fixed_scale(precision),
                      terms, forces, dudl, n_pairs);
   return hipGetLastError();
 }
