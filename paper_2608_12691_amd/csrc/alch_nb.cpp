@@ -556,7 +556,6 @@ static alch_nb_status enqueue_compute(alch_nb_ctx* ctx, const double* pos, const
   hipStream_t st = ctx->stream;
   HIPCHK(launch_prepare(d, st, pos, lam, mode, 0.5 * p.skin, p.schedule));
   HIPCHK(launch_list_build(d, st, pos, ctx->r_list, sh, ctx->fused_blocks));
-  HIPCHK(launch_canon(d, st, pos, p.precision));
   const bool timed = allow_timing && ctx->timing && ctx->n_timed < kTimingSlots;
   if (timed) HIPCHK(hipEventRecord(ctx->ev[2 * ctx->n_timed], st));
   HIPCHK(launch_tile(d, st, ctx->pc, p.precision, p.schedule, sh, pos));

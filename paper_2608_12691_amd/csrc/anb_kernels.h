@@ -36,7 +36,6 @@ hipError_t launch_export(const Dev& d, hipStream_t st, double r_list, int* out, 
 hipError_t launch_init(const Dev& d, hipStream_t st);
 hipError_t launch_prepare(const Dev& d, hipStream_t st, const double* pos, const double* lambda, int mode,
                           double half_skin, int schedule);
-hipError_t launch_canon(const Dev& d, hipStream_t st, const double* pos, int precision);
 hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
                        const TileShape& shape, const double* xin);
 hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int schedule, double* terms,

@@ -338,14 +338,28 @@ __device__ void ph_build_sc(const Dev& d) {
         d.cl_bbox[c * 6 + 3 + k] = cnt ? chi[k] : 0.0;
       }
     }
-    if (l == 0) {
-      for (int k = 0; k < 3; ++k) {
-        const double a0 = n ? slo[k] : 0.0, a1 = n ? shi[k] : 0.0;
+    double org[3];
+    for (int k = 0; k < 3; ++k) {
+      const double a0 = n ? slo[k] : 0.0, a1 = n ? shi[k] : 0.0;
+      org[k] = 0.5 * (a0 + a1);
+      if (l == 0) {
         d.sc_bbox[s * 6 + k] = a0;
         d.sc_bbox[s * 6 + 3 + k] = a1;
-        d.sc_origin[s * 3 + k] = 0.5 * (a0 + a1);
+        d.sc_origin[s * 3 + k] = org[k];
       }
     }
+    // coordinates relative to the SC origin for the first evaluation on
+    // this list (the positions are those of the build), and cleared force
+    // accumulators; later calls refresh them in the prepare pass
+    double q[3] = {0.0, 0.0, 0.0};
+    if (v)
+      for (int k = 0; k < 3; ++k) q[k] = w[k] - org[k];
+    d.pos32[sl] = make_float4((float)q[0], (float)q[1], (float)q[2], d.q32[sl]);
+    d.pos64[sl] = make_double4(q[0], q[1], q[2], d.q64[sl]);
+    const int slots = d.sc_cap * kSc;
+    d.ffix[sl] = 0ull;
+    d.ffix[slots + sl] = 0ull;
+    d.ffix[2 * slots + sl] = 0ull;
   }
 }
 

@@ -649,11 +649,8 @@ __global__ void __launch_bounds__(kBlk) k_prepare(Dev d, const double* __restric
   bool moved = false, bad = false;
   for (int a = t; a < d.n_atoms; a += gthreads()) {
     const double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
-      bad = true;
-      continue;
-    }
-    if (!have_list || mode == 2) continue;
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) bad = true;  // reported; the values still flow
+    if (!have_list || mode == 2) continue;  // the list build writes the slot data
     const ReplicaInfo& rp = d.reps[d.grids[d.atom_grid[a]].replica];
     double dd[3] = {x - d.x_build[3 * a], y - d.x_build[3 * a + 1], z - d.x_build[3 * a + 2]};
     double r2 = 0;
@@ -662,6 +659,19 @@ __global__ void __launch_bounds__(kBlk) k_prepare(Dev d, const double* __restric
       r2 += dd[k] * dd[k];
     }
     if (r2 > half_skin2) moved = true;
+    // Coordinates relative to the atom's SC origin in the image it had at
+    // the build (displacement since the build plus the build-time offset),
+    // and cleared force accumulators.  If this call rebuilds the list, the
+    // build overwrites them for the new slots.
+    const int sl = d.atom_slot[a], s = sl / kSc;
+    double q[3];
+    for (int k = 0; k < 3; ++k) q[k] = dd[k] + (d.xw[3 * a + k] - d.sc_origin[3 * s + k]);
+    d.pos32[sl] = make_float4((float)q[0], (float)q[1], (float)q[2], d.q32[sl]);
+    d.pos64[sl] = make_double4(q[0], q[1], q[2], d.q64[sl]);
+    const int slots = d.sc_cap * kSc;
+    d.ffix[sl] = 0ull;
+    d.ffix[slots + sl] = 0ull;
+    d.ffix[2 * slots + sl] = 0ull;
   }
   if (bad) atomicOr(d.flags, 4u);
   if (moved) {
@@ -677,46 +687,6 @@ hipError_t launch_prepare(const Dev& d, hipStream_t st, const double* pos, const
   return hipGetLastError();
 }
 
-// Super-cluster-local coordinates (minimum image about the SC origin), the
-// charge in the w component, and zeroed force accumulators.
-template <typename R>
-__global__ void __launch_bounds__(kBlk) k_canon(Dev d, const double* __restrict__ pos) {
-  using P4 = typename C4<R>::P4;
-  P4* out = reinterpret_cast<P4*>(sizeof(R) == 4 ? (void*)d.pos32 : (void*)d.pos64);
-  const int slots = d.sc_cap * kSc;
-  for (int sl = gtid(); sl < slots; sl += gthreads()) {
-    const int s = sl / kSc;
-    if (d.sc_n[s] == 0) continue;
-    d.ffix[sl] = 0ull;
-    d.ffix[slots + sl] = 0ull;
-    d.ffix[2 * slots + sl] = 0ull;
-    const int a = d.slot_atom[sl];
-    P4 v;
-    double q[3] = {0.0, 0.0, 0.0};
-    if (a < 0) {
-      v.x = v.y = v.z = v.w = R(0);
-    } else {
-      const ReplicaInfo& rp = d.reps[d.grids[d.atom_grid[a]].replica];
-      for (int k = 0; k < 3; ++k) q[k] = local_coord(d, pos, a, s, k, rp.box[k]);
-      v.x = (R)q[0];
-      v.y = (R)q[1];
-      v.z = (R)q[2];
-      v.w = sizeof(R) == 4 ? (R)d.q32[sl] : (R)d.q64[sl];
-    }
-    out[sl] = v;
-    // the FP32 path's solute-solvent pairs take their displacements from
-    // these FP64 coordinates
-    if (sizeof(R) == 4) d.pos64[sl] = make_double4(q[0], q[1], q[2], 0.0);
-  }
-}
-
-hipError_t launch_canon(const Dev& d, hipStream_t st, const double* pos, int precision) {
-  const int slots = d.sc_cap * kSc;
-  const int g = max(1, min(4096, (slots + kBlk - 1) / kBlk));
-  if (precision == 0) hipLaunchKernelGGL(k_canon<float>, dim3(g), dim3(kBlk), 0, st, d, pos);
-  else hipLaunchKernelGGL(k_canon<double>, dim3(g), dim3(kBlk), 0, st, d, pos);
-  return hipGetLastError();
-}
 
 // Blocks [0, K * kRedChunks): block (k, c) sums chunk c of box k's unit
 // partials (fixed chunk bounds and tree order); the last chunk of box k to
