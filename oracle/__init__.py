@@ -53,6 +53,9 @@ def _load():
             lib.oracle_pairs.restype = i
             lib.oracle_atom_energy.argtypes = [i, i, P, P, P, i, P, P, i, P, P, P, d, d, d, d, i, d]
             lib.oracle_atom_energy.restype = d
+            lib.oracle_atoms_terms.argtypes = [i, P, i, P, P, P, i, P, P, i, P, P, P, d, d, d, d, i, d, P, P, P, P,
+                                               i]
+            lib.oracle_atoms_terms.restype = i
             lib.oracle_pair_probe.argtypes = [d, d, d, d, i, d, d, d, d, i, d, P]
             lib.oracle_pair_probe.restype = None
             lib.oracle_lbf_switches.argtypes = [d, P]
@@ -152,6 +155,28 @@ def atom_energy(a, system, ff, params: Params, lam, positions=None):
                                   _ptr(bx), sg.shape[0], _ptr(sg), _ptr(ep), _ptr(ch), params.cutoff,
                                   params.switch_width, params.dsf_alpha, params.sc_alpha, params.schedule,
                                   float(lam))
+
+
+def atoms_terms(sel, system, ff, params: Params, lam, positions=None, n_threads=0):
+    """Per-atom sums for the atoms in sel: dict(forces [S,3] = -dU/dx_a, energy [S]
+    (pair energies involving a), dudl [S] (its solute-solvent pairs), n_pairs [S])."""
+    lib = _load()
+    sl = _c(sel, np.int32)
+    pos = _c(system.positions if positions is None else positions, np.float64).reshape(-1, 3)
+    t = _c(system.types, np.int32)
+    s = _c(system.is_solute, np.uint8)
+    ex = _c(system.exclusions, np.int32).reshape(-1, 2)
+    bx = _c(system.box, np.float64)
+    sg, ep, ch = _c(ff.sigma, np.float64), _c(ff.epsilon, np.float64), _c(ff.charge, np.float64)
+    S = sl.shape[0]
+    f, e, dl, npair = np.zeros((S, 3)), np.zeros(S), np.zeros(S), np.zeros(S, np.int64)
+    rc = lib.oracle_atoms_terms(S, _ptr(sl), pos.shape[0], _ptr(pos), _ptr(t), _ptr(s), ex.shape[0], _ptr(ex),
+                                _ptr(bx), sg.shape[0], _ptr(sg), _ptr(ep), _ptr(ch), params.cutoff,
+                                params.switch_width, params.dsf_alpha, params.sc_alpha, params.schedule, float(lam),
+                                _ptr(f), _ptr(e), _ptr(dl), _ptr(npair), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle_atoms_terms rejected its input (code %d)" % rc)
+    return dict(forces=f, energy=e, dudl=dl, n_pairs=npair)
 
 
 def pair_probe(r, sig, eps, qq, alchemical, params: Params, lam):

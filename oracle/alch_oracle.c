@@ -501,6 +501,76 @@ double oracle_atom_energy(int a, int n, const double *pos, const int32_t *type, 
   return ks_val(&e);
 }
 
+/*
+ * Per-atom sums for a selection of atoms (the plain definition restricted to
+ * the pairs that involve each selected atom a): the force on a, -dU/dx_a,
+ * the sum of the pair energies of a, the sum of the lambda derivatives of
+ * its solute-solvent pairs and the number of its pairs within the cutoff.
+ * Summed over all solute atoms the derivatives give dU/dlambda of the box,
+ * since every solute-solvent pair has exactly one solute atom.  Outputs
+ * [n_sel][3], [n_sel], [n_sel], [n_sel]; O(n) per selected atom.
+ */
+int oracle_atoms_terms(int n_sel, const int32_t *sel, int n, const double *pos, const int32_t *type,
+                       const uint8_t *is_solute, int n_excl, const int32_t *excl, const double *box, int n_types,
+                       const double *sigma, const double *epsilon, const double *charge, double cutoff,
+                       double switch_width, double dsf_alpha, double sc_alpha, int schedule, double lambda,
+                       double *force, double *energy, double *dudl, int64_t *n_pairs, int n_threads) {
+  if (n < 0 || cutoff <= 0 || (schedule != SCHED_BEUTLER && schedule != SCHED_LBF)) return -1;
+  for (int d = 0; d < 3; ++d)
+    if (!(box[d] >= 2.0 * cutoff)) return -4;
+  for (int i = 0; i < n; ++i)
+    if (type[i] < 0 || type[i] >= n_types) return -5;
+  for (int s = 0; s < n_sel; ++s)
+    if (sel[s] < 0 || sel[s] >= n) return -7;
+  excl_index ix;
+  if (excl_build(n, n_excl, excl, &ix) != 0) return -6;
+  or_params p = {cutoff, switch_width, dsf_alpha, sc_alpha, schedule};
+  lam_state ls;
+  lam_state_init(lambda, schedule, &ls);
+  double *w = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+  for (int i = 0; i < n; ++i) wrap3(pos + 3 * i, box, w + 3 * i);
+  const double rc2 = cutoff * cutoff;
+#ifdef _OPENMP
+  int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
+#else
+  (void)n_threads;
+#endif
+  for (int s = 0; s < n_sel; ++s) {
+    const int a = sel[s];
+    ksum e = {0, 0}, dl = {0, 0}, f[3] = {{0, 0}, {0, 0}, {0, 0}};
+    int64_t cnt = 0;
+    for (int j = 0; j < n; ++j) {
+      if (j == a) continue;
+      const int lo = a < j ? a : j, hi = a < j ? j : a;
+      double d[3];
+      /* canonical displacement of the pair (hi - lo), as in the full sum */
+      double r2 = min_image(w + 3 * lo, w + 3 * hi, box, d);
+      if (!(r2 < rc2)) continue;
+      if (is_excluded(&ix, lo, hi)) continue;
+      const int ti = type[lo], tj = type[hi];
+      const int alch = (is_solute[lo] != 0) != (is_solute[hi] != 0);
+      const double r = sqrt(r2);
+      pair_out o;
+      eval_pair(r, 0.5 * (sigma[ti] + sigma[tj]), sqrt(epsilon[ti] * epsilon[tj]), charge[ti] * charge[tj], alch,
+                &p, &ls, &o);
+      ++cnt;
+      ks_add(&e, alch ? o.ss_vdw + o.ss_elec : o.u_plain);
+      if (alch) ks_add(&dl, o.dl_vdw + o.dl_elec);
+      /* force on hi is -dU/dr d/r, on lo the opposite */
+      const double sgn = (a == hi) ? 1.0 : -1.0;
+      for (int k = 0; k < 3; ++k) ks_add(&f[k], sgn * (-o.du_dr * d[k] / r));
+    }
+    for (int k = 0; k < 3; ++k) force[3 * s + k] = ks_val(&f[k]);
+    energy[s] = ks_val(&e);
+    dudl[s] = ks_val(&dl);
+    n_pairs[s] = cnt;
+  }
+  free(w);
+  free(ix.start);
+  return 0;
+}
+
 /* Single-pair probe for closed-form tests: writes
  * out = {u, -du/dr, du/dlambda, du/dsig, du/deps, du/dqq}. */
 void oracle_pair_probe(double r, double sig, double eps, double qq, int alchemical, double cutoff,

@@ -603,20 +603,207 @@ def _octanol_ff_types():
             [OCT_TYPES[n]["charge"] for n in names])
 
 
-def _pack_octanol(rng, pk, n_mol, lo, hi, type_of, base_mol_id, parts):
+def _place_batch(a, b, c, bond, angle_deg, torsion_deg):
+    """_place for M reference triples at once: a, b, c [M,3], torsion [M] (degrees)."""
+    bc = c - b
+    bc /= np.linalg.norm(bc, axis=1, keepdims=True)
+    n = np.cross(b - a, bc)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    m = np.cross(n, bc)
+    th = np.deg2rad(angle_deg)
+    ph = np.deg2rad(np.asarray(torsion_deg, float))[:, None]
+    return c - bond * np.cos(th) * bc + bond * np.sin(th) * (np.cos(ph) * m + np.sin(ph) * n)
+
+
+def octanol_conformers_aligned(rng, n_draw):
+    """Octanol-like chains for dense packing, drawn as a batch: backbone
+    dihedrals trans-biased (180 deg with probability 0.8, else +-65 deg
+    gauche, each +N(0, 8 deg)), hydroxyl and methyl torsions uniform;
+    self-clashing draws are rejected as in octanol_conformer.  Each kept
+    chain is centred with its heavy-atom principal axis along z.  Returns
+    [M, 27, 3] with M <= n_draw."""
     names, bonds = octanol_topology()
-    excl = _exclusions_within(27, bonds, 3)
+    gd = _graph_distances(27, bonds)
     heavy = np.array([n not in ("H", "HO") for n in names])
-    sites, _ = _lattice_sites(rng, n_mol, lo, hi)
+    M = n_draw
+    x = np.zeros((M, 27, 3))
+    x[:, 2] = [OCT_CO, 0.0, 0.0]
+    x[:, 3] = _place([0.0, 1.0, 0.0], x[0, 0], x[0, 2], OCT_CC, TETRA_DEG, 180.0)
+    x[:, 1] = _place_batch(x[:, 3], x[:, 2], x[:, 0], OCT_OH, TETRA_DEG, rng.uniform(0, 360, M))
+    for c in range(4, 10):
+        a = 0 if c == 4 else c - 3
+        u = rng.uniform(size=M)
+        base = np.where(u < 0.8, 180.0, np.where(u < 0.9, 65.0, -65.0))
+        x[:, c] = _place_batch(x[:, a], x[:, c - 2], x[:, c - 1], OCT_CC, TETRA_DEG, base + rng.normal(0.0, 8.0, M))
+    h = 10
+    for k in range(1, 9):
+        c = 1 + k
+        prev = 0 if k == 1 else c - 1
+        if k < 8:
+            for tors in (120.0, -120.0):
+                x[:, h] = _place_batch(x[:, c + 1], x[:, prev], x[:, c], OCT_CH, TETRA_DEG, np.full(M, tors))
+                h += 1
+        else:
+            t0 = rng.uniform(0, 360, M)
+            for dt in (0.0, 120.0, 240.0):
+                x[:, h] = _place_batch(x[:, c - 2], x[:, prev], x[:, c], OCT_CH, TETRA_DEG, t0 + dt)
+                h += 1
+    d = np.linalg.norm(x[:, :, None, :] - x[:, None, :, :], axis=-1)
+    far = gd >= 4
+    hh = heavy[:, None] & heavy[None, :]
+    ok = ~(np.any(far & hh & (d < 2.5), axis=(1, 2)) | np.any(far & ~hh & (d < 1.5), axis=(1, 2)))
+    x = x[ok] - x[ok].mean(axis=1, keepdims=True)
+    out = np.empty_like(x)
+    for i in range(len(x)):
+        _, v = np.linalg.eigh(np.cov(x[i][heavy].T))
+        axis = v[:, -1] if v[2, -1] >= 0 else -v[:, -1]
+        out[i] = x[i] @ _rotation_onto_z(axis).T
+    return out
+
+
+def _rotation_onto_z(u):
+    """Rotation matrix taking the unit vector u onto +z (Rodrigues)."""
+    z = np.array([0.0, 0.0, 1.0])
+    v = np.cross(u, z)
+    s, c = np.linalg.norm(v), float(u @ z)
+    if s < 1e-12:
+        return np.eye(3) if c > 0 else np.diag([1.0, -1.0, -1.0])
+    k = v / s
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    ang = np.arctan2(s, c)
+    return np.eye(3) + np.sin(ang) * K + (1 - np.cos(ang)) * (K @ K)
+
+
+def _z_turn(rng):
+    """Uniform rotation about z, then an end-over-end flip with probability 1/2."""
+    t = rng.uniform(0.0, 2.0 * np.pi)
+    c, s = np.cos(t), np.sin(t)
+    r = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+    return r @ np.diag([1.0, -1.0, -1.0]) if rng.uniform() < 0.5 else r
+
+
+class _SlotPacker:
+    """Molecules on lattice slots with clash removal by redrawing.
+
+    Each movable molecule has a draw function returning its absolute
+    coordinates.  Intermolecular pairs closer than MIN_HEAVY (heavy-heavy)
+    or MIN_WITH_H (involving H) are clashes; per round one partner of every
+    clash is redrawn.  A molecule redrawn max_redraws times is removed (the
+    achieved count is recorded by the caller: the density is never changed
+    silently).
+    """
+
+    def __init__(self, rng, box):
+        self.rng = rng
+        self.box = np.asarray(box, float)
+        self.coords, self.heavy, self.draw, self.redraws = [], [], [], []
+
+    def add(self, heavy, draw=None, coords=None):
+        self.coords.append(draw() if coords is None else np.asarray(coords, float))
+        self.heavy.append(np.asarray(heavy, bool))
+        self.draw.append(draw)
+        self.redraws.append(0)
+
+    def _flat(self, alive):
+        idx = np.nonzero(alive)[0]
+        pos = np.concatenate([self.coords[m] for m in idx])
+        mol = np.concatenate([np.full(len(self.coords[m]), m) for m in idx])
+        heavy = np.concatenate([self.heavy[m] for m in idx])
+        return pos, mol, heavy
+
+    def _clashes(self, pos, mol, heavy, tree, query_mask=None):
+        """Clashing molecule pairs; with query_mask, only atoms it selects are queried."""
+        if query_mask is None:
+            pairs = tree.query_pairs(r=MIN_HEAVY, output_type="ndarray")
+        else:
+            qi = np.nonzero(query_mask)[0]
+            lists = tree.query_ball_point(_wrap(pos[qi], self.box), r=MIN_HEAVY)
+            a = np.repeat(qi, [len(l) for l in lists])
+            b = np.concatenate([np.asarray(l, int) for l in lists]) if len(lists) else np.zeros(0, int)
+            pairs = np.stack([a, b], 1) if len(a) else np.zeros((0, 2), int)
+        if pairs.size == 0:
+            return np.zeros((0, 2), int)
+        pairs = pairs[mol[pairs[:, 0]] != mol[pairs[:, 1]]]
+        if pairs.size == 0:
+            return np.zeros((0, 2), int)
+        d = pos[pairs[:, 1]] - pos[pairs[:, 0]]
+        d -= self.box * np.round(d / self.box)
+        r = np.linalg.norm(d, axis=1)
+        bad = np.where(heavy[pairs[:, 0]] & heavy[pairs[:, 1]], r < MIN_HEAVY, r < MIN_WITH_H)
+        return np.stack([mol[pairs[bad, 0]], mol[pairs[bad, 1]]], 1)
+
+    def run(self, max_rounds=3000, max_redraws=200):
+        alive = np.ones(len(self.coords), bool)
+        moved = None
+        for rnd in range(max_rounds):
+            pos, mol, heavy = self._flat(alive)
+            tree = cKDTree(_wrap(pos, self.box), boxsize=self.box)
+            qmask = None if moved is None else np.isin(mol, list(moved))
+            bad = self._clashes(pos, mol, heavy, tree, qmask)
+            if len(bad) == 0:
+                if moved is None:
+                    return alive, rnd
+                moved = None  # confirm with a full check
+                continue
+            # redraw one partner per clash: the molecule just moved when the
+            # check was local (bad[:, 0] holds it), else the second one
+            redo = set()
+            for a, b in bad:
+                order = (a, b) if moved is not None else (b, a)
+                cand = [int(m) for m in order if self.draw[m] is not None]
+                if cand and not (set(cand) & redo):
+                    redo.add(cand[0])
+            if not redo:
+                raise RuntimeError("packer: clash between fixed molecules")
+            for m in redo:
+                self.redraws[m] += 1
+                if self.redraws[m] > max_redraws:
+                    alive[m] = False
+                else:
+                    self.coords[m] = self.draw[m]()
+            moved = {m for m in redo if alive[m]}
+        raise RuntimeError("packer: clashes remain after %d rounds" % max_rounds)
+
+
+def _octanol_slots(rng, pk, n_mol, lo, hi, counts, pool_size=4096):
+    """n_mol aligned octanol chains on a random subset of a counts[0] x
+    counts[1] x counts[2] lattice in [lo, hi): a conformer drawn from a pool
+    of pool_size batch draws, a random turn about z, flip, jitter U(+-0.3) A
+    in x, y and U(+-0.45) A in z."""
+    pool = octanol_conformers_aligned(rng, pool_size)
+    names, bonds = octanol_topology()
+    heavy = np.array([n not in ("H", "HO") for n in names])
+    lo, hi = np.asarray(lo, float), np.asarray(hi, float)
+    ext = hi - lo
+    grids = [lo[d] + (np.arange(counts[d]) + 0.5) * ext[d] / counts[d] for d in range(3)]
+    g = np.stack(np.meshgrid(*grids, indexing="ij"), axis=-1).reshape(-1, 3)
+    if g.shape[0] < n_mol:
+        raise ValueError("lattice too small for %d molecules" % n_mol)
+    sites = g[np.sort(rng.choice(g.shape[0], size=n_mol, replace=False))]
     first = len(pk.coords)
-    for s in sites:
-        x, _, _ = octanol_conformer(rng)
-        pk.add(x, s, heavy, template=lambda: octanol_conformer(rng)[0], jitter=0.5)
-    return first, excl, np.array([type_of[n] for n in names])
+    for site in sites:
+        def draw(site=site):
+            j = rng.uniform(-1.0, 1.0, 3) * np.array([0.3, 0.3, 0.45])
+            return pool[rng.integers(len(pool))] @ _z_turn(rng).T + site + j
+        pk.add(heavy, draw)
+    return first
+
+
+def _delete_near(pk, ref_index, dmin, first):
+    """Remove movable molecules (index >= first) with an atom closer than dmin to molecule ref_index."""
+    tree = cKDTree(_wrap(pk.coords[ref_index], pk.box), boxsize=pk.box)
+    keep = list(range(first))
+    for m in range(first, len(pk.coords)):
+        d, _ = tree.query(_wrap(pk.coords[m], pk.box), k=1)
+        if np.min(d) >= dmin:
+            keep.append(m)
+    for name in ("coords", "heavy", "draw", "redraws"):
+        lst = getattr(pk, name)
+        setattr(pk, name, [lst[m] for m in keep])
 
 
 def make_config3(seed=None, n_octanol=1480, L=73.0):
-    """20-atom flexible solute in 1,480 octanol-like chains, 73 A cube."""
+    """20-atom flexible solute in 1,480 octanol-like chains, 73 A cube (104 atoms/nm^3)."""
     seed = config_seed(3) if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
     onames, osig, oeps, ochg = _octanol_ff_types()
@@ -625,41 +812,29 @@ def make_config3(seed=None, n_octanol=1480, L=73.0):
     ff = ForceField(sigma=np.array(osig + list(s_sig)), epsilon=np.array(oeps + list(s_eps)),
                     charge=np.array(ochg + list(s_q)), names=onames + ["S%d" % i for i in range(20)])
     type_of = {n: i for i, n in enumerate(onames)}
+    names, bonds = octanol_topology()
+    oexcl = _exclusions_within(27, bonds, 3)
+    otypes = np.array([type_of[n] for n in names])
     box = np.full(3, L)
-    pk = _Packer(rng, box)
-    pk.add(sol, box / 2, np.ones(20, bool), fixed=True)
-    first, oexcl, otypes = _pack_octanol(rng, pk, n_octanol, np.zeros(3), box, type_of, 1, None)
-    _drop_overlapping(pk, 0, SOLUTE_WATER_DELETE)
-    n_iter = pk.repair()
+    pk = _SlotPacker(rng, box)
+    pk.add(np.ones(20, bool), coords=sol - sol.mean(axis=0) + box / 2)
+    counts = np.array([16, 16, 6])   # 4.56 x 4.56 x 12.2 A cells for ~12 A chains
+    _octanol_slots(rng, pk, n_octanol, np.zeros(3), box, counts)
+    _delete_near(pk, 0, SOLUTE_WATER_DELETE, 1)
+    alive, rounds = pk.run()
     parts = [dict(pos=pk.coords[0], types=np.arange(5, 25), solute=np.ones(20), mol=np.zeros(20),
                   excl=_exclusions_within(20, sbonds, 3))]
-    for m in range(1, len(pk.coords)):
+    for m in np.nonzero(alive)[0][1:]:
         parts.append(dict(pos=pk.coords[m], types=otypes, solute=np.zeros(27), mol=np.full(27, m), excl=oexcl))
     s = _assemble(parts, box)
-    s.info.update(n_octanol_requested=n_octanol, n_octanol=len(pk.coords) - 1, repair_iterations=int(n_iter))
+    s.info.update(n_octanol_requested=n_octanol, n_octanol=len(parts) - 1, packing_rounds=int(rounds))
     return Workload(name="octanol1480_solute20", systems=[s], ff=ff, cutoff=10.0, skin=1.0, switch_width=1.0,
                     dsf_alpha=0.2, sc_alpha=0.5, lambdas=np.array([0.3]), seed=seed,
                     info=dict(fd_lambdas=[0.3, 0.7, 1.0]))
 
 
-def _drop_overlapping(pk, fixed_index, dmin):
-    ref = pk.coords[fixed_index]
-    tree = cKDTree(_wrap(ref, pk.box), boxsize=pk.box)
-    keep = []
-    for m in range(len(pk.coords)):
-        if m == fixed_index:
-            keep.append(m)
-            continue
-        d, _ = tree.query(_wrap(pk.coords[m], pk.box), k=1)
-        if np.min(d) >= dmin:
-            keep.append(m)
-    for name in ("coords", "centers", "mol_templates", "heavy", "fixed"):
-        lst = getattr(pk, name)
-        setattr(pk, name, [lst[m] for m in keep])
-
-
 def make_config5(seed=None, L=135.0, n_total=250_000):
-    """250k-atom water/octanol slab with a 22-atom peptide-like solute."""
+    """250k-atom water/octanol slab with a 22-atom peptide-like solute in the water half."""
     seed = config_seed(5) if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
     wn, wsig, weps, wchg = _water_forcefield_types()
@@ -670,26 +845,28 @@ def make_config5(seed=None, L=135.0, n_total=250_000):
                     charge=np.array(wchg + ochg + list(s_q)),
                     names=wn + onames + ["P%d" % i for i in range(22)])
     type_of = {n: 2 + i for i, n in enumerate(onames)}
+    names, bonds = octanol_topology()
+    oexcl = _exclusions_within(27, bonds, 3)
+    otypes = np.array([type_of[n] for n in names])
     box = np.full(3, L)
-    half_vol = L * L * L / 2
-    n_w_atoms = int(round(0.1 * half_vol))
-    n_w = n_w_atoms // 3
+    n_w = int(round(0.1 * L * L * L / 2)) // 3
     n_oct = (n_total - 22 - 3 * n_w) // 27
-    pk = _Packer(rng, box)
-    centre = np.array([L / 2, L / 2, L / 4])
-    pk.add(sol, centre, np.ones(22, bool), fixed=True)
+    pk = _SlotPacker(rng, box)
+    pk.add(np.ones(22, bool), coords=sol - sol.mean(axis=0) + np.array([L / 2, L / 2, L / 4]))
     sites, _ = _lattice_sites(rng, n_w, np.zeros(3), np.array([L, L, L / 2]))
     wf = water_molecule_frame()
-    for s in sites:
-        pk.add(wf, s, np.array([True, False, False]), jitter=0.3)
-    n_water_slots = len(pk.coords)
-    _, oexcl, otypes = _pack_octanol(rng, pk, n_oct, np.array([0, 0, L / 2]), np.array([L, L, L]), type_of, 0, None)
-    _drop_overlapping(pk, 0, SOLUTE_WATER_DELETE)
-    n_iter = pk.repair()
+    wheavy = np.array([True, False, False])
+    for site in sites:
+        pk.add(wheavy, lambda site=site: wf @ _random_rotation(rng).T + site + rng.uniform(-0.3, 0.3, 3))
+    first_oct = len(pk.coords)
+    counts = np.array([31, 31, 5])   # 4.35 x 4.35 x 13.5 A cells
+    _octanol_slots(rng, pk, n_oct, np.array([0.0, 0.0, L / 2]), np.array([L, L, L]), counts)
+    _delete_near(pk, 0, SOLUTE_WATER_DELETE, 1)
+    alive, rounds = pk.run()
     parts = [dict(pos=pk.coords[0], types=np.arange(7, 29), solute=np.ones(22), mol=np.zeros(22),
                   excl=_exclusions_within(22, sbonds, 3))]
     nw = no = 0
-    for m in range(1, len(pk.coords)):
+    for m in np.nonzero(alive)[0][1:]:
         if len(pk.coords[m]) == 3:
             parts.append(dict(pos=pk.coords[m], types=np.array([0, 1, 1]), solute=np.zeros(3), mol=np.full(3, m),
                               excl=[(0, 1), (0, 2), (1, 2)]))
@@ -698,8 +875,9 @@ def make_config5(seed=None, L=135.0, n_total=250_000):
             parts.append(dict(pos=pk.coords[m], types=otypes, solute=np.zeros(27), mol=np.full(27, m), excl=oexcl))
             no += 1
     s = _assemble(parts, box)
-    s.info.update(n_waters=nw, n_octanol=no, repair_iterations=int(n_iter), cv=PEPTIDE_CV)
-    del n_water_slots
+    s.info.update(n_waters_requested=n_w, n_waters=nw, n_octanol_requested=n_oct, n_octanol=no,
+                  packing_rounds=int(rounds), cv=PEPTIDE_CV)
+    del first_oct
     return Workload(name="slab250k_peptide22", systems=[s], ff=ff, cutoff=12.0, skin=1.0, switch_width=1.0,
                     dsf_alpha=0.2, sc_alpha=0.5, lambdas=np.array([0.7]), seed=seed,
                     info=dict(cv_atoms=np.array(list(PEPTIDE_CV.values()), np.int32)))

@@ -390,3 +390,37 @@ def test_input_validation():
     with pytest.raises(ValueError):
         O.evaluate(np.zeros((2, 3)), [0, 0], [0, 0], np.array([[1, 0]]), np.full(3, 30.0), [3.0], [0.1], [0.0],
                    P_BEU, 0.5)  # exclusion with i > j
+
+
+def test_atoms_terms_restrict_the_full_sum(cfg1):
+    """Per-atom sums: forces equal the full evaluation's, the solute atoms'
+    lambda derivatives add up to dU/dlambda (each solute-solvent pair has one
+    solute atom), and the atom energies count every pair twice."""
+    s, ff, P = _box(cfg1)
+    for sched, lam in ((O.BEUTLER, 0.3), (O.BEUTLER, 0.8), (O.LBF, 0.6)):
+        P.schedule = sched
+        full = O.evaluate_system(s, ff, P, lam)
+        every = np.arange(s.n_atoms)
+        at = O.atoms_terms(every, s, ff, P, lam)
+        np.testing.assert_allclose(at["forces"], full["forces"], rtol=1e-12, atol=1e-11)
+        assert at["n_pairs"].sum() == 2 * full["n_pairs"]
+        assert at["energy"].sum() == pytest.approx(2 * full["terms"][8], rel=1e-12)
+        solu = np.nonzero(s.is_solute)[0]
+        assert O.atoms_terms(solu, s, ff, P, lam)["dudl"].sum() == pytest.approx(full["terms"][9], rel=1e-12)
+        # the per-atom energy is the atom-energy function of the FD tests
+        for a in (0, int(solu[0]), s.n_atoms - 1):
+            assert at["energy"][a] == pytest.approx(O.atom_energy(a, s, ff, P, lam), rel=1e-13)
+    P.schedule = O.BEUTLER
+
+
+def test_atoms_terms_force_is_minus_gradient(cfg1):
+    s, ff, P = _box(cfg1)
+    lam, h = 0.65, 1e-5
+    atoms = np.array([1, 40, int(np.nonzero(s.is_solute)[0][2])])
+    f = O.atoms_terms(atoms, s, ff, P, lam)["forces"]
+    for i, a in enumerate(atoms):
+        for k in range(3):
+            xp = s.positions.copy(); xp[a, k] += h
+            xm = s.positions.copy(); xm[a, k] -= h
+            fd = -(O.atom_energy(a, s, ff, P, lam, xp) - O.atom_energy(a, s, ff, P, lam, xm)) / (2 * h)
+            assert f[i, k] == pytest.approx(fd, rel=2e-6, abs=2e-7)
