@@ -14,7 +14,6 @@ headline), the FP64 path beside it, the tile kernel's roofline position and
 the CPU oracle timed on a bounded sample.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -33,14 +32,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("tile_kernels.hip", "anb_internal.h", "erfc_coeffs.h"):
-        with open(os.path.join(ROOT, "paper_2608_12691_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic(name):
     """HBM bytes per tile launch from a committed counter summary, if it was
     taken on the current kernel source (else None)."""
@@ -49,6 +40,7 @@ def measured_traffic(name):
         return None
     with open(path) as fh:
         rec = json.load(fh)
+    from paper_2608_12691_amd.profiling import kernel_source_hash
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -167,6 +159,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="after the run, copy a device buffer of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -257,6 +251,13 @@ def main():
         line["hrex16"] = batched_vs_single(torch, args.batched_steps, 20, args.mode == "graph")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, traj_np, lams_np, W, args.cpu_calls)
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = int(src.numel())
     print(json.dumps(line), flush=True)
 
 
