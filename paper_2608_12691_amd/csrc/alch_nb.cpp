@@ -30,8 +30,8 @@ struct Variant {
 };
 // Launch variants of the tile kernel searched by alch_nb_autotune().
 constexpr Variant kVariants[] = {
-    {8, 16, 0, 1024, 0}, {8, 16, 2, 1024, 1}, {8, 16, 2, 1024, 2}, {8, 16, 4, 1024, 2},
-    {8, 64, 0, 1024, 0}, {8, 16, 8, 1024, 2}, {8, 24, 4, 1024, 2}, {8, 12, 4, 1024, 2},
+    {8, 16, 0, 1024, 0}, {8, 16, 0, 1280, 0}, {8, 12, 0, 1024, 0}, {8, 24, 0, 1024, 0},
+    {8, 64, 0, 1024, 0}, {8, 16, 2, 1024, 1}, {4, 16, 0, 1024, 0}, {8, 16, 0, 2048, 0},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr bool variants_fit() {

@@ -486,6 +486,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
           const R r2 = dx * dx + dy * dy + dz * dz;
           // the pair mask is a lane mask: combine it on the scalar unit
           const unsigned long long inm = __ballot(r2 < P.rc2) & mcur[c];
+          if (inm == 0) continue;  // the whole 64-pair tile has moved out of range
           npair += __popcll(inm);
           const bool inr = __builtin_amdgcn_inverse_ballot_w64(inm);
           PairCore<R, SW> pc;
@@ -651,7 +652,7 @@ __global__ void __launch_bounds__(kBlk) k_prepare(Dev d, const double* __restric
     const double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
     if (!(isfinite(x) && isfinite(y) && isfinite(z))) bad = true;  // reported; the values still flow
     if (!have_list || mode == 2) continue;  // the list build writes the slot data
-    const ReplicaInfo& rp = d.reps[d.grids[d.atom_grid[a]].replica];
+    const ReplicaInfo& rp = d.reps[d.atom_rep[a]];
     double dd[3] = {x - d.x_build[3 * a], y - d.x_build[3 * a + 1], z - d.x_build[3 * a + 2]};
     double r2 = 0;
     for (int k = 0; k < 3; ++k) {
@@ -751,16 +752,18 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
     return;
   }
   if (!forces) return;
+  // one force component per thread
   const int slots = d.sc_cap * kSc;
-  for (int a = (blockIdx.x - nred) * blockDim.x + threadIdx.x; a < d.n_atoms; a += (gridDim.x - nred) * blockDim.x) {
-    const int sl = d.atom_slot[a];
-    for (int c = 0; c < 3; ++c) forces[3 * a + c] = (double)(long long)d.ffix[c * slots + sl] * inv_scale;
+  const int n3 = 3 * d.n_atoms;
+  for (int i = (blockIdx.x - nred) * blockDim.x + threadIdx.x; i < n3; i += (gridDim.x - nred) * blockDim.x) {
+    const int a = i / 3, c = i - 3 * a;
+    forces[i] = (double)(long long)d.ffix[c * slots + d.atom_slot[a]] * inv_scale;
   }
 }
 
 hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int schedule, double* terms, double* forces,
                            double* dudl, long long* n_pairs) {
-  const int gf = forces ? max(1, min(1024, (d.n_atoms + kBlk - 1) / kBlk)) : 0;
+  const int gf = forces ? max(1, min(2048, (3 * d.n_atoms + kBlk - 1) / kBlk)) : 0;
   hipLaunchKernelGGL(k_finalize, dim3(d.n_reps * kRedChunks + gf), dim3(kBlk), 0, st, d, schedule,
                      1.0 / fixed_scale(precision),
                      terms, forces, dudl, n_pairs);
