@@ -26,12 +26,11 @@ using namespace anb;
 namespace {
 
 struct Variant {
-  int epu, tiles, ecost, blocks, part;  // entries and tiles per unit at most, entry cost, blocks, partition
+  int epu, tiles, blocks;  // entries and tiles (past the first entry) per unit at most, blocks of the launch
 };
 // Launch variants of the tile kernel searched by alch_nb_autotune().
 constexpr Variant kVariants[] = {
-    {8, 16, 0, 1024, 0}, {8, 16, 0, 1280, 0}, {8, 12, 0, 1024, 0}, {8, 24, 0, 1024, 0},
-    {8, 64, 0, 1024, 0}, {8, 16, 2, 1024, 1}, {4, 16, 0, 1024, 0}, {8, 16, 0, 2048, 0},
+    {8, 16, 1024}, {8, 12, 1024}, {8, 24, 1024}, {8, 16, 1280}, {4, 16, 1024}, {8, 64, 1024}, {8, 16, 2048},
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 constexpr bool variants_fit() {
@@ -172,8 +171,6 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->flags = cv.take<unsigned int>(base, 1);
   d->rebuild = cv.take<int>(base, 1);
   d->barrier = cv.take<unsigned int>(base, kBarWords);
-  d->unit_cost = cv.take<int>(base, U);
-  d->wave_ustart = cv.take<int>(base, kMaxWaves + 1);
   d->pos32 = cv.take<float4>(base, SL);
   d->pos64 = cv.take<double4>(base, SL);
   d->ffix = cv.take<unsigned long long>(base, 3 * SL);
@@ -536,8 +533,6 @@ static TileShape shape_of(const alch_nb_ctx* ctx) {
   TileShape s;
   s.epu = v.epu;
   s.tiles = v.tiles;
-  s.ecost = v.ecost;
-  s.part = v.part;
   const long long need = ((long long)ctx->unit_cap + 3) / 4;
   long long b = std::min<long long>(v.blocks, std::max<long long>(8, need));
   b = std::min<long long>((b + 7) / 8 * 8, kMaxWaves / 4);
@@ -590,7 +585,7 @@ alch_nb_status alch_nb_set_variant(alch_nb_ctx* ctx, int32_t variant) {
   if (!ctx || variant < 0 || variant >= kNumVariants) return ALCH_NB_E_INVALID_ARG;
   ctx->variant = variant;
   destroy_graph(ctx);
-  if (ctx->bound) HIPCHK(launch_units(ctx->dev, ctx->stream, shape_of(ctx)));  // units and partition of this shape
+  if (ctx->bound) HIPCHK(launch_units(ctx->dev, ctx->stream, shape_of(ctx)));  // units of this shape
   return ALCH_NB_OK;
 }
 

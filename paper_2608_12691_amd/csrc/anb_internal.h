@@ -24,11 +24,11 @@ constexpr int kSc = 64;          // atom slots per super-cluster
 constexpr int kBarGroups = 8;
 constexpr int kBarStride = 16;  // counters on separate 64-byte lines
 constexpr int kBarWords = kBarStride * (kBarGroups + 1);
-// work partition of the tile kernel: at most kMaxWaves waves per launch
+// the tile kernel's launch has at most kMaxWaves waves
 constexpr int kMaxWaves = 8192;
-constexpr int kUnitOverhead = 2;  // per-unit cost, in 64-pair tiles, of the partition
 constexpr int kRedChunks = 16;   // unit chunks per box in the final reduction
 constexpr int kAlchTileCost = 8;  // cost of a solute-solvent tile, in plain tiles
+constexpr uint32_t kUnitStart = 1u << 31;  // ent_info bit: a work unit starts at this entry
 constexpr int kStrips = 8;       // search waves per super-cluster (neighbour columns dealt round-robin)
 constexpr double kKe = 332.06371;
 constexpr int kNTerms = 10;  // energy-term slots per box
@@ -129,8 +129,6 @@ struct Dev {
   unsigned int* flags;       // [1] sticky flags
   int* rebuild;              // [1]
   unsigned int* barrier;     // [kBarWords] grid barrier: top count, generation, group counts
-  int* unit_cost;            // [U] tiles + overhead, then its exclusive prefix
-  int* wave_ustart;          // [kMaxWaves+1] first unit of each wave of the tile launch
   // per call
   float4* pos32;             // [SC*64] local x, y, z, q
   double4* pos64;            // [SC*64]
@@ -145,7 +143,7 @@ struct Dev {
   const double4* tp64;       // [T*T]
 };
 
-enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6, CTR_PART_W = 7 };
+enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6 };
 
 constexpr int kPgBlocks = 512;  // blocks of the parameter-gradient pass
 constexpr int kMaxTypes = 256;  // atom types supported by the parameter-gradient pass

@@ -18,9 +18,7 @@ constexpr int kMaxEpu = 8;  // entries per work unit at most (LDS staging of j-f
 struct TileShape {
   int epu;      // entries per work unit at most
   int tiles;    // 64-pair tiles per work unit at most (past its first entry)
-  int ecost;    // cost of an entry, in tiles, in the partition over waves
-  int blocks;   // blocks of 256 threads (4 waves)
-  int part;     // 0: equal unit counts per wave; 1: cost-balanced runs, XCD-major; 2: cost-balanced runs
+  int blocks;   // blocks of 256 threads (4 waves); waves take equal runs of units
 };
 
 // fused_blocks > 0: one launch of the fused build with that many blocks
@@ -30,7 +28,7 @@ hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, do
 // Resident blocks per compute unit of the fused list kernel (0 on error).
 int list_fused_max_blocks();
 // work units and their partition over the waves of a tile launch of this shape
-hipError_t launch_units(const Dev& d, hipStream_t st, const TileShape& shape);
+hipError_t launch_units(const Dev& d, hipStream_t st, const TileShape& shape);  // work units of this shape
 hipError_t launch_export(const Dev& d, hipStream_t st, double r_list, int* out, long long cap,
                          unsigned long long* counter);
 hipError_t launch_init(const Dev& d, hipStream_t st);

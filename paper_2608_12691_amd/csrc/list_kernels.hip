@@ -494,77 +494,60 @@ __device__ void ph_scan_entries(const Dev& d) {
   __syncthreads();
 }
 
-// One block, after the mask pass: work units, replica ranges and the
-// partition of the units over the W waves of a tile launch.  A unit is a run
-// of one SC's entries, cut greedily where it would exceed epu entries or,
-// past its first entry, tcap tiles (the tile counts are the pruned masks').
-// The waves take contiguous runs of units of about equal cost (tiles plus a
-// per-entry and per-unit overheads): unit u goes to wave floor(P_u W / P) for the exclusive
-// cost prefix P_u and total P, so the runs follow the unit order.
-// Tiles of an entry as counted by the unit cuts and the partition: a
-// solute-solvent tile takes its inputs from FP64 data and its pair
-// parameters from the type-pair table, about kAlchTileCost plain tiles.
+// Work units, after the mask pass, in three passes.  A unit is a run of
+// one SC's entries, cut greedily where it would exceed epu entries or, past
+// its first entry, tcap tiles (the pruned masks' counts; a solute-solvent
+// tile, fed from FP64 data and the type-pair table, counts kAlchTileCost).
+
+__device__ inline bool entry_is_alch(uint32_t info) { return ((info >> 8) & 3u) == KIND_ALCH; }
 __device__ inline int entry_cost_tiles(uint32_t info) {
   const int t = __popc(info & 0xffu);
-  return ((info >> 8) & 3u) == KIND_ALCH ? kAlchTileCost * t : t;
+  return entry_is_alch(info) ? kAlchTileCost * t : t;
 }
 
-__device__ void ph_units(const Dev& d, int epu, int tcap, int ecost, int W) {
+// Pass A, one wave per SC: the greedy cuts (scalar, over each 64-entry
+// chunk), marked with kUnitStart in ent_info; unit count per SC.
+__device__ void ph_units_count(const Dev& d, int epu, int tcap) {
+  const int lane = threadIdx.x & 63;
   const bool ok_all = d.ctr[CTR_NENT] == d.ctr[CTR_ENT_NEED];
-  const int n = d.sc_cap;
-  for (int s = threadIdx.x; s < n; s += blockDim.x) {
+  for (int s = gwave(); s < d.sc_cap; s += gwaves()) {
     const int cnt = ok_all ? d.sc_ecount[s] : 0;
     const int e0 = d.sc_estart[s];
     int nu = 0, ne = 0, nt = 0;
-    for (int e = e0; e < e0 + cnt; ++e) {
-      const int t = entry_cost_tiles(d.ent_info[e]);
-      if (ne == 0 || ne == epu || nt + t > tcap) {
-        ++nu;
-        ne = 0;
-        nt = 0;
+    for (int base = 0; base < cnt; base += 64) {
+      const int e = e0 + base + lane;
+      const bool valid = base + lane < cnt;
+      const uint32_t info = valid ? d.ent_info[e] : 0u;
+      const int t = entry_cost_tiles(info);
+      const int m = min(64, cnt - base);
+      unsigned long long start = 0;
+      for (int l = 0; l < m; ++l) {
+        const int tl = __builtin_amdgcn_readlane(t, l);
+        if (ne == 0 || ne == epu || nt + tl > tcap) {
+          start |= 1ull << l;
+          ++nu;
+          ne = 0;
+          nt = 0;
+        }
+        ++ne;
+        nt += tl;
       }
-      ++ne;
-      nt += t;
+      if (valid) d.ent_info[e] = (info & ~kUnitStart) | (((start >> lane) & 1ull) ? kUnitStart : 0u);
     }
-    d.sc_ustart[s] = nu;
+    if (lane == 0) d.sc_ustart[s] = nu;
   }
-  __syncthreads();
+}
+
+// Pass B, one block: offsets of each SC's units, counters, replica ranges.
+__device__ void ph_units_scan(const Dev& d) {
+  const int n = d.sc_cap;
   const int total = block_scan_array(d.sc_ustart, d.sc_ustart, n);
   const bool fits = total <= d.unit_cap;
   if (threadIdx.x == 0) {
     d.ctr[CTR_UNIT_NEED] = total;
     d.ctr[CTR_NUNIT] = fits ? total : 0;
-    d.ctr[CTR_PART_W] = W;
     if (!fits) atomicOr(d.flags, 16u);
   }
-  const int nu_all = fits ? total : 0;
-  if (fits) {
-    for (int s = threadIdx.x; s < n; s += blockDim.x) {
-      const int cnt = ok_all ? d.sc_ecount[s] : 0;
-      if (cnt == 0) continue;
-      const int e0 = d.sc_estart[s];
-      const int rep = d.grids[d.col_grid[d.sc_col[s]]].replica;
-      int u = d.sc_ustart[s] - 1, ne = 0, nt = 0, b0 = e0;
-      for (int e = e0; e < e0 + cnt; ++e) {
-        const int t = entry_cost_tiles(d.ent_info[e]);
-        if (ne == 0 || ne == epu || nt + t > tcap) {
-          if (ne > 0) {
-            d.units[u] = make_int4(s, b0, e, rep);
-            d.unit_cost[u] = nt + ecost * ne + kUnitOverhead;
-          }
-          ++u;
-          ne = 0;
-          nt = 0;
-          b0 = e;
-        }
-        ++ne;
-        nt += t;
-      }
-      d.units[u] = make_int4(s, b0, e0 + cnt, rep);
-      d.unit_cost[u] = nt + ecost * ne + kUnitOverhead;
-    }
-  }
-  __syncthreads();
   for (int k = threadIdx.x; k <= d.n_reps; k += blockDim.x) {
     int v;
     if (!fits) v = 0;
@@ -572,20 +555,40 @@ __device__ void ph_units(const Dev& d, int epu, int tcap, int ecost, int W) {
     else v = d.reps[k].sc_begin < n ? d.sc_ustart[d.reps[k].sc_begin] : total;
     d.rep_ustart[k] = v;
   }
-  // cost partition over the waves
-  const int ptot = block_scan_array(d.unit_cost, d.unit_cost, nu_all);
-  if (nu_all == 0) {
-    for (int w = threadIdx.x; w <= W; w += blockDim.x) d.wave_ustart[w] = 0;
-  } else {
-    for (int u = threadIdx.x; u < nu_all; u += blockDim.x) {
-      const int wu = (int)((long long)d.unit_cost[u] * W / ptot);
-      const int wp = u == 0 ? -1 : (int)((long long)d.unit_cost[u - 1] * W / ptot);
-      for (int w = wp + 1; w <= wu; ++w) d.wave_ustart[w] = u;
-      if (u == nu_all - 1)
-        for (int w = wu + 1; w <= W; ++w) d.wave_ustart[w] = nu_all;
-    }
-  }
   __syncthreads();
+}
+
+// Pass C, one wave per SC: the unit table (a unit ends where the next one
+// starts, the last at the SC's end).
+__device__ void ph_units_fill(const Dev& d) {
+  const int lane = threadIdx.x & 63;
+  if (d.ctr[CTR_UNIT_NEED] > d.unit_cap) return;
+  const bool ok_all = d.ctr[CTR_NENT] == d.ctr[CTR_ENT_NEED];
+  int* ucol = reinterpret_cast<int*>(d.units);
+  for (int s = gwave(); s < d.sc_cap; s += gwaves()) {
+    const int cnt = ok_all ? d.sc_ecount[s] : 0;
+    if (cnt == 0) continue;
+    const int e0 = d.sc_estart[s], u0 = d.sc_ustart[s];
+    const int rep = d.grids[d.col_grid[d.sc_col[s]]].replica;
+    int u = u0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int base = 0; base < cnt; base += 64) {
+      const int e = e0 + base + lane;
+      const bool valid = base + lane < cnt;
+      const uint32_t info = valid ? d.ent_info[e] : 0u;
+      const bool st = valid && (info & kUnitStart);
+      const unsigned long long S = __ballot(st);
+      if (st) {
+        const int idx = u + __popcll(S & below);
+        ucol[4 * idx + 0] = s;
+        ucol[4 * idx + 1] = e;
+        ucol[4 * idx + 3] = rep;
+        if (idx > u0) ucol[4 * (idx - 1) + 2] = e;  // the previous unit ends here
+      }
+      u += __popcll(S);
+    }
+    if (lane == 0) ucol[4 * (u - 1) + 2] = e0 + cnt;
+  }
 }
 
 __device__ inline bool is_excluded(const Dev& d, int a, int b) {
@@ -673,9 +676,17 @@ __global__ void __launch_bounds__(kBlk) k_build_sc(Dev d) { GATED; ph_build_sc(d
 __global__ void __launch_bounds__(kBlk) k_search_count(Dev d, double rlm) { GATED; ph_search<false>(d, rlm); }
 __global__ void __launch_bounds__(kBlk) k_scan_entries(Dev d) { GATED; ph_scan_entries(d); }
 __global__ void __launch_bounds__(kBlk) k_search_write(Dev d, double rlm) { GATED; ph_search<true>(d, rlm); }
-__global__ void __launch_bounds__(kBlk) k_units(Dev d, int epu, int tcap, int ecost, int waves, int force) {
+__global__ void __launch_bounds__(kBlk) k_units_count(Dev d, int epu, int tcap, int force) {
   if (!force) { GATED; }
-  ph_units(d, epu, tcap, ecost, waves);
+  ph_units_count(d, epu, tcap);
+}
+__global__ void __launch_bounds__(kBlk) k_units_scan(Dev d, int force) {
+  if (!force) { GATED; }
+  ph_units_scan(d);
+}
+__global__ void __launch_bounds__(kBlk) k_units_fill(Dev d, int force) {
+  if (!force) { GATED; }
+  ph_units_fill(d);
 }
 __global__ void __launch_bounds__(kBlk) k_masks(Dev d, double rl2) { GATED; ph_masks(d, rl2); }
 __global__ void __launch_bounds__(kBlk) k_end(Dev d) { GATED; ph_end(d); }
@@ -738,7 +749,7 @@ __device__ inline void grid_barrier(const Dev& d, unsigned int& gen, Serial seri
 // The whole list build in one launch (phases separated by grid barriers;
 // the one-block scans run inside the barriers).
 __global__ void __launch_bounds__(kBlk) k_list_fused(Dev d, const double* __restrict__ pos, double rlm, double rl2,
-                                                     int epu, int tcap, int ecost, int waves) {
+                                                     int epu, int tcap) {
   if (!rebuild_on(d)) return;
   __shared__ unsigned int gen_s;
   if (threadIdx.x == 0) gen_s = __hip_atomic_load(&d.barrier[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -758,18 +769,22 @@ __global__ void __launch_bounds__(kBlk) k_list_fused(Dev d, const double* __rest
   ph_search<true>(d, rlm);
   grid_barrier(d, gen, none);
   ph_masks(d, rl2);
-  grid_barrier(d, gen, [&] { ph_units(d, epu, tcap, ecost, waves); });
+  grid_barrier(d, gen, none);
+  ph_units_count(d, epu, tcap);
+  grid_barrier(d, gen, [&] { ph_units_scan(d); });
+  ph_units_fill(d);
+  grid_barrier(d, gen, none);
   ph_end(d);
 }
 
 hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, double r_list, const TileShape& sh,
                              int fused_blocks) {
-  const int epu = sh.epu, tcap = sh.tiles, ecost = sh.ecost, waves = sh.blocks * 4;
+  const int epu = sh.epu, tcap = sh.tiles;
   const double rlm = r_list * (1.0 + 1e-12) + 1e-9;  // conservative box test
   const double rl2 = rlm * rlm;  // masks keep the same margin; the export test is exact
   const dim3 B(kBlk);
   if (fused_blocks > 0) {
-    hipLaunchKernelGGL(k_list_fused, dim3(fused_blocks), B, 0, st, d, pos, rlm, rl2, epu, tcap, ecost, waves);
+    hipLaunchKernelGGL(k_list_fused, dim3(fused_blocks), B, 0, st, d, pos, rlm, rl2, epu, tcap);
     return hipGetLastError();
   }
   const int g_atoms = clampi((d.n_atoms + kBlk - 1) / kBlk, 1, 256);
@@ -785,7 +800,9 @@ hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, do
   hipLaunchKernelGGL(k_scan_entries, dim3(1), B, 0, st, d);
   hipLaunchKernelGGL(k_search_write, dim3(g_srch), B, 0, st, d, rlm);
   hipLaunchKernelGGL(k_masks, dim3(g_ent), B, 0, st, d, rl2);
-  hipLaunchKernelGGL(k_units, dim3(1), B, 0, st, d, epu, tcap, ecost, waves, 0);
+  hipLaunchKernelGGL(k_units_count, dim3(g_sc), B, 0, st, d, epu, tcap, 0);
+  hipLaunchKernelGGL(k_units_scan, dim3(1), B, 0, st, d, 0);
+  hipLaunchKernelGGL(k_units_fill, dim3(g_sc), B, 0, st, d, 0);
   hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, st, d);
   return hipGetLastError();
 }
@@ -799,7 +816,10 @@ int list_fused_max_blocks() {
 }
 
 hipError_t launch_units(const Dev& d, hipStream_t st, const TileShape& sh) {
-  hipLaunchKernelGGL(k_units, dim3(1), dim3(kBlk), 0, st, d, sh.epu, sh.tiles, sh.ecost, sh.blocks * 4, 1);
+  const int g_sc = clampi((d.sc_cap + kWpb - 1) / kWpb, 1, 256);
+  hipLaunchKernelGGL(k_units_count, dim3(g_sc), dim3(kBlk), 0, st, d, sh.epu, sh.tiles, 1);
+  hipLaunchKernelGGL(k_units_scan, dim3(1), dim3(kBlk), 0, st, d, 1);
+  hipLaunchKernelGGL(k_units_fill, dim3(g_sc), dim3(kBlk), 0, st, d, 1);
   return hipGetLastError();
 }
 

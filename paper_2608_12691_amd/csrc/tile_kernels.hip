@@ -266,7 +266,7 @@ __device__ inline void alch_pair(R dx, R dy, R dz, bool valid, const typename C4
 }
 
 template <typename R, int SCHED, bool SW>
-__global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Pot<R> P, int part, double fscale, const double* __restrict__ xin) {
+__global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Pot<R> P, double fscale, const double* __restrict__ xin) {
   using P4 = typename C4<R>::P4;
   using P2 = typename C4<R>::P2;
   const P4* __restrict__ pos = reinterpret_cast<const P4*>(sizeof(R) == 4 ? (const void*)d.pos32 : (const void*)d.pos64);
@@ -300,28 +300,13 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   P2* ise = ise_all + (threadIdx.x & ~63);
   const int il = lane & 7, jl = lane >> 3;
   const int n_units = d.ctr[CTR_NUNIT];
-  // Unit range of this wave.  Blocks are dispatched round-robin over the 8
-  // XCDs; with xcd set, XCD x (blocks b with b % 8 == x) takes the x-th
-  // eighth of the waves' runs of the list-build partition (runs of about
-  // equal cost, neighbouring super-clusters kept together, so shared
-  // j-clusters stay in that XCD's L2).  Otherwise, or when the partition
-  // was made for another launch shape, waves take equal runs of units.
-  // The wave index is made provably uniform: unit and entry indices then
-  // live in scalar registers and their loads are scalar loads.
+  // Unit range of this wave: equal runs of units (the unit cuts already cap
+  // each unit's tiles).  The wave index is made provably uniform: unit and
+  // entry indices then live in scalar registers and their loads are scalar.
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nw = gridDim.x * (kBlk / 64);
-  int ub, ue;
-  if (part && (gridDim.x & 7) == 0 && as_const(d.ctr)[CTR_PART_W] == nw) {
-    const int r = part == 1 ? (blockIdx.x & 7) * (nw >> 3) + (blockIdx.x >> 3) * (kBlk / 64) + wib
-                            : blockIdx.x * (kBlk / 64) + wib;
-    const cptr<int> ws = as_const(d.wave_ustart);
-    ub = ws[r];
-    ue = ws[r + 1];
-  } else {
-    const int w = blockIdx.x * (kBlk / 64) + wib;
-    ub = (int)((long long)n_units * w / nw);
-    ue = (int)((long long)n_units * (w + 1) / nw);
-  }
+  const int nw = gridDim.x * (kBlk / 64), w = blockIdx.x * (kBlk / 64) + wib;
+  const int ub = (int)((long long)n_units * w / nw);
+  const int ue = (int)((long long)n_units * (w + 1) / nw);
   // i-forces of the current super-cluster, carried over consecutive units
   // of the same super-cluster; they leave when it changes: summed over jl,
   // lane (jl, il) then takes i-cluster c = jl so that lane l holds slot
@@ -569,20 +554,20 @@ hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int pr
   if (precision == 0) {
     const Pot<float> P = make_pot<float>(pc);
     if (schedule == 0) {
-      if (sw) hipLaunchKernelGGL((k_tile<float, 0, true>), G, B, 0, st, d, P, sh.part, fs, xin);
-      else hipLaunchKernelGGL((k_tile<float, 0, false>), G, B, 0, st, d, P, sh.part, fs, xin);
+      if (sw) hipLaunchKernelGGL((k_tile<float, 0, true>), G, B, 0, st, d, P, fs, xin);
+      else hipLaunchKernelGGL((k_tile<float, 0, false>), G, B, 0, st, d, P, fs, xin);
     } else {
-      if (sw) hipLaunchKernelGGL((k_tile<float, 1, true>), G, B, 0, st, d, P, sh.part, fs, xin);
-      else hipLaunchKernelGGL((k_tile<float, 1, false>), G, B, 0, st, d, P, sh.part, fs, xin);
+      if (sw) hipLaunchKernelGGL((k_tile<float, 1, true>), G, B, 0, st, d, P, fs, xin);
+      else hipLaunchKernelGGL((k_tile<float, 1, false>), G, B, 0, st, d, P, fs, xin);
     }
   } else {
     const Pot<double> P = make_pot<double>(pc);
     if (schedule == 0) {
-      if (sw) hipLaunchKernelGGL((k_tile<double, 0, true>), G, B, 0, st, d, P, sh.part, fs, xin);
-      else hipLaunchKernelGGL((k_tile<double, 0, false>), G, B, 0, st, d, P, sh.part, fs, xin);
+      if (sw) hipLaunchKernelGGL((k_tile<double, 0, true>), G, B, 0, st, d, P, fs, xin);
+      else hipLaunchKernelGGL((k_tile<double, 0, false>), G, B, 0, st, d, P, fs, xin);
     } else {
-      if (sw) hipLaunchKernelGGL((k_tile<double, 1, true>), G, B, 0, st, d, P, sh.part, fs, xin);
-      else hipLaunchKernelGGL((k_tile<double, 1, false>), G, B, 0, st, d, P, sh.part, fs, xin);
+      if (sw) hipLaunchKernelGGL((k_tile<double, 1, true>), G, B, 0, st, d, P, fs, xin);
+      else hipLaunchKernelGGL((k_tile<double, 1, false>), G, B, 0, st, d, P, fs, xin);
     }
   }
   return hipGetLastError();
