@@ -123,10 +123,12 @@ struct PairCore {
 // ------------------------------------------------------------ DPP helpers
 
 // sum over the 8 lanes of each lane group (lane & ~7): quad_perm xor 1, xor 2, row_half_mirror
+// (every source lane exists, so bound_ctrl changes nothing but lets the
+// compiler fold each lane move into its add)
 __device__ inline float red8(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));
   return v;
 }
 __device__ inline double dpp_d(double v, int ctrl) {
@@ -158,6 +160,64 @@ __device__ inline R red_jl(R v) {
   v += __shfl_xor(v, 32);
   return v;
 }
+// Reduce-scatter of the i-forces over jl: in[c] is lane (jl, il)'s
+// contribution to atom il of i-cluster c; the result in lane (jl, il) is
+// the sum over jl of in[jl], i.e. the total for slot c * 8 + il with c = jl.
+// Three halving steps: lanes 32 apart (jl bit 2) with v_permlane32_swap,
+// 16 apart (jl bit 1) with v_permlane16_swap, 8 apart (jl bit 0) with a
+// row rotation by 8.
+__device__ inline void swap32(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+__device__ inline void swap16(float& a, float& b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+__device__ inline void swap32(double& a, double& b) {
+  const long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)x, (unsigned)y, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+  a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ inline void swap16(double& a, double& b) {
+  const long long x = __double_as_longlong(a), y = __double_as_longlong(b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)x, (unsigned)y, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(x >> 32), (unsigned)(y >> 32), false, false);
+  a = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+  b = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+__device__ inline float ror8(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x128, 0xF, 0xF, true));
+}
+__device__ inline double ror8(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), 0x128, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x128, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename R>
+__device__ inline R scatter_jl(R (&in)[8], bool odd8) {
+  R p[4], q[2];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    R a = in[c], b = in[c + 4];
+    swap32(a, b);
+    p[c] = a + b;  // lanes 0-31: cluster c; lanes 32-63: cluster c + 4
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    R a = p[c], b = p[c + 2];
+    swap16(a, b);
+    q[c] = a + b;  // even rows: + 0; odd rows: + 2
+  }
+  const R keep = odd8 ? q[1] : q[0], send = odd8 ? q[0] : q[1];
+  return keep + ror8(send);
+}
+
 __device__ inline double wave_sum(double v) {
   for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
   return v;
@@ -185,12 +245,21 @@ __device__ inline void wave_sync() {
 // Fixed-point add of one value per active lane with no per-lane branch
 // around the atomic; out-of-range or NaN values add zero and raise the
 // overflow flag.
+// Below 2^51 the integer nearest to x is read from the bits of
+// x + 1.5 * 2^52 (round to nearest even, as __double2ll_rn); larger values,
+// rare, take the general conversion.
 template <typename R>
 __device__ inline void add_fixed_lanes(unsigned long long* p, R v, double scale, unsigned int* flags, bool active) {
   const double x = (double)v * scale;
-  const bool ok = fabs(x) < 4.611686018427388e18;  // |f| < 2^62 / scale
-  if (__ballot(active && !ok) && (threadIdx.x & 63) == 0) atomicOr(flags, 1u);
-  if (active) atomicAdd(p, ok ? (unsigned long long)__double2ll_rn(x) : 0ull);
+  unsigned long long q;
+  if (__builtin_expect(__ballot(active && !(fabs(x) < 2251799813685248.0)) != 0, 0)) {
+    const bool ok = fabs(x) < 4.611686018427388e18;  // |f| < 2^62 / scale
+    if (__ballot(active && !ok) && (threadIdx.x & 63) == 0) atomicOr(flags, 1u);
+    q = ok ? (unsigned long long)__double2ll_rn(x) : 0ull;
+  } else {
+    q = (unsigned long long)(__double_as_longlong(x + 6755399441055744.0) - 0x4338000000000000ll);
+  }
+  if (active) atomicAdd(p, q);
 }
 
 // ------------------------------------------------------------ tile kernel
@@ -298,6 +367,10 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   double* rare3 = &rare_all[3][threadIdx.x];
   P4* ipos = ipos_all + (threadIdx.x & ~63);
   P2* ise = ise_all + (threadIdx.x & ~63);
+  // i-forces of the solute-solvent entries of the current super-cluster,
+  // already summed over jl (slot c * 8 + il of each component)
+  __shared__ R fia_all[kBlk / 64][3][kSc];
+  R* fia = &fia_all[threadIdx.x >> 6][0][0];
   const int il = lane & 7, jl = lane >> 3;
   const int n_units = d.ctr[CTR_NUNIT];
   // Unit range of this wave: equal runs of units (the unit cuts already cap
@@ -314,16 +387,11 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   R fix[kScCl], fiy[kScCl], fiz[kScCl];
   int cur_s = -1;
   auto flush_i = [&](int sc) {
-    R gx = R(0), gy = R(0), gz = R(0);
-#pragma unroll
-    for (int c = 0; c < kScCl; ++c) {
-      const R fx = red_jl(fix[c]), fy = red_jl(fiy[c]), fz = red_jl(fiz[c]);
-      if (jl == c) {
-        gx = fx;
-        gy = fy;
-        gz = fz;
-      }
-    }
+    const bool odd8 = (lane & 8) != 0;
+    wave_sync();
+    R gx = scatter_jl(fix, odd8) + fia[lane];
+    R gy = scatter_jl(fiy, odd8) + fia[kSc + lane];
+    R gz = scatter_jl(fiz, odd8) + fia[2 * kSc + lane];
     const int sl = sc * kSc + lane;
     add_fixed_lanes(d.ffix + sl, gx, fscale, d.flags, true);
     add_fixed_lanes(d.ffix + slots + sl, gy, fscale, d.flags, true);
@@ -351,6 +419,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       wave_sync();
       ipos[lane] = pos[s * kSc + lane];
       ise[lane] = se[s * kSc + lane];
+      fia[lane] = fia[kSc + lane] = fia[2 * kSc + lane] = R(0);
       wave_sync();
 #pragma unroll
       for (int c = 0; c < kScCl; ++c) fix[c] = fiy[c] = fiz[c] = R(0);
@@ -362,6 +431,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     bool rare = false;  // wave-uniform: the unit had a solute-solute or solute-solvent entry
     *rare0 = *rare1 = *rare2 = *rare3 = 0.0;
     int npair = 0;
+    unsigned long long alch_bits;
     // j-cluster data of all entries of the unit, one load per lane: lane
     // (k, t) takes atom t of entry U.y + k (units hold at most 8 entries)
     {
@@ -371,9 +441,11 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       v.x = v.y = v.z = v.w = R(0);
       q.x = q.y = R(0);
       int jsl = 0;
+      uint32_t inf = 0;
       if (e < U.z) {
         const int jc = d.ent_jc[e];
-        const int code = (int)((d.ent_info[e] >> 16) & 31u);
+        inf = d.ent_info[e];
+        const int code = (int)((inf >> 16) & 31u);
         const int sj = jc >> 3;
         jsl = jc * kCl + t;
         v = pos[jsl];
@@ -391,102 +463,138 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       jse[lane] = q;
       jslb[lane] = jsl;
       wave_sync();
+      // one bit per solute-solvent entry (bit 8 k)
+      alch_bits = __ballot(e < U.z && t == 0 && ((inf >> 8) & 3u) == (uint32_t)KIND_ALCH);
     }
-    // entry words and pair masks one entry ahead (scalar loads)
     const cptr<uint32_t> einfo = as_const(d.ent_info);
-    uint32_t info_a = einfo[U.y];
     const cptr<unsigned long long> emask = as_const(d.ent_mask);
+    // Plain entries (solvent-solvent and solute-solute); entry words and
+    // pair masks are read one entry ahead (scalar loads).
+    uint32_t info_a = einfo[U.y];
     unsigned long long m_a[kScCl];
 #pragma unroll
     for (int c = 0; c < kScCl; ++c) m_a[c] = emask[(size_t)U.y * kScCl + c];
     for (int e = U.y; e < U.z; ++e) {
+      const int k = e - U.y;  // entry slot in this unit
       unsigned long long mcur[kScCl];
 #pragma unroll
       for (int c = 0; c < kScCl; ++c) mcur[c] = m_a[c];
       const uint32_t info = info_a;
       if (e + 1 < U.z) {
+        info_a = einfo[e + 1];
 #pragma unroll
         for (int c = 0; c < kScCl; ++c) m_a[c] = emask[(size_t)(e + 1) * kScCl + c];
-        info_a = einfo[e + 1];
       }
-      const int k = e - U.y;  // entry slot in this unit
+      if (((info >> 8) & 3u) == (uint32_t)KIND_ALCH) continue;  // second pass
       const uint32_t imask = info & 0xffu;
-      const int kind = (int)((info >> 8) & 3u);
-      const int jsl = jslb[k * kCl + jl];
       R fjx = R(0), fjy = R(0), fjz = R(0), eent = R(0);
-      if (kind == KIND_ALCH) {
-        // FP64 local coordinates (written by the canon pass for every slot),
-        // moved into this entry's image and rounded once per displacement
-        const int code = (int)((info >> 16) & 31u);
-        const int sj = jsl >> 6;
-        const double odx = d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
-        const double ody = d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
-        const double odz = d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
-        const double4 pj64 = pos64[jsl];
-        const double xj = pj64.x + odx, yj = pj64.y + ody, zj = pj64.z + odz;
-        const int tj = d.slot_type[jsl];
-        double a0 = 0, a1 = 0, a2 = 0;
+      const P4 pj = jpos[k * kCl + jl];
+      const P2 qj = jse[k * kCl + jl];
+      const R xj = pj.x, yj = pj.y, zj = pj.z;
+      // i-cluster data one cluster ahead (LDS reads are always in bounds)
+      P4 pin = ipos[il];
+      P2 qin = ise[il];
 #pragma unroll
-        for (int c = 0; c < kScCl; ++c) {
-          if (!(imask & (1u << c))) continue;
-          const int isl = s * kSc + c * kCl + il;
-          const double4 pi64 = pos64[isl];
-          const R dx = (R)(xj - pi64.x), dy = (R)(yj - pi64.y), dz = (R)(zj - pi64.z);
-          const P4 tp = tpair[d.slot_type[isl] * T + tj];
-          R u, fr, rinv2;
-          bool inr;
-          const bool valid = __builtin_amdgcn_inverse_ballot_w64(mcur[c]);
-          alch_pair<R, SCHED, SW>(dx, dy, dz, valid, tp, la0, la1, P, u, fr, rinv2, inr, a0, a1, a2);
-          npair += __popcll(__ballot(inr));
-          const R fs = inr ? fr * rinv2 : R(0);
-          const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
-          fjx += fx;
-          fjy += fy;
-          fjz += fz;
-          fix[c] -= fx;
-          fiy[c] -= fy;
-          fiz[c] -= fz;
+      for (int c = 0; c < kScCl; ++c) {
+        const P4 pi = pin;
+        const P2 qi = qin;
+        if (c + 1 < kScCl) {
+          pin = ipos[(c + 1) * kCl + il];
+          qin = ise[(c + 1) * kCl + il];
         }
-        *rare1 += a0;
-        *rare2 += a1;
-        *rare3 += a2;
-        rare = true;
+        if (!(imask & (1u << c))) continue;
+        const R dx = xj - pi.x, dy = yj - pi.y, dz = zj - pi.z;
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        // the pair mask is a lane mask: combine it on the scalar unit
+        const unsigned long long inm = __ballot(r2 < P.rc2) & mcur[c];
+        if (inm == 0) continue;  // the whole 64-pair tile has moved out of range
+        npair += __popcll(inm);
+        const bool inr = __builtin_amdgcn_inverse_ballot_w64(inm);
+        PairCore<R, SW> pc;
+        pc.eval(r2, inr, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P);
+        const R u = pc.lj0 * pc.S + pc.el;
+        const R fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
+        const R fs = inr ? fr * pc.rinv2 : R(0);
+        eent += inr ? u : R(0);
+        const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
+        fjx += fx;
+        fjy += fy;
+        fjz += fz;
+        fix[c] -= fx;
+        fiy[c] -= fy;
+        fiz[c] -= fz;
+      }
+      fjx = red8(fjx);
+      fjy = red8(fjy);
+      fjz = red8(fjz);
+      if (il == 0) {
+        P4 v;
+        v.x = fjx;
+        v.y = fjy;
+        v.z = fjz;
+        v.w = R(0);
+        jf[k * kCl + jl] = v;
+      }
+      if (((info >> 8) & 3u) == (uint32_t)KIND_SOLV) {
+        acc_solv += (double)eent;
       } else {
-        const P4 pj = jpos[k * kCl + jl];
-        const P2 qj = jse[k * kCl + jl];
-        const R xj = pj.x, yj = pj.y, zj = pj.z;
-        // i-cluster data one cluster ahead (LDS reads are always in bounds)
-        P4 pin = ipos[il];
-        P2 qin = ise[il];
+        *rare0 += (double)eent;
+        rare = true;
+      }
+    }
+    // Solute-solvent entries (rare): FP64 local coordinates (written by the
+    // canon pass for every slot) moved into the entry's image and rounded
+    // once per displacement; i-forces summed over jl into LDS.  The register
+    // i-forces move to LDS first, so they hold no registers in this pass.
+    if (alch_bits) {
+      const bool odd8 = (lane & 8) != 0;
+      const R gx = scatter_jl(fix, odd8), gy = scatter_jl(fiy, odd8), gz = scatter_jl(fiz, odd8);
+      wave_sync();
+      fia[lane] += gx;
+      fia[kSc + lane] += gy;
+      fia[2 * kSc + lane] += gz;
+      wave_sync();
 #pragma unroll
-        for (int c = 0; c < kScCl; ++c) {
-          const P4 pi = pin;
-          const P2 qi = qin;
-          if (c + 1 < kScCl) {
-            pin = ipos[(c + 1) * kCl + il];
-            qin = ise[(c + 1) * kCl + il];
-          }
-          if (!(imask & (1u << c))) continue;
-          const R dx = xj - pi.x, dy = yj - pi.y, dz = zj - pi.z;
-          const R r2 = dx * dx + dy * dy + dz * dz;
-          // the pair mask is a lane mask: combine it on the scalar unit
-          const unsigned long long inm = __ballot(r2 < P.rc2) & mcur[c];
-          if (inm == 0) continue;  // the whole 64-pair tile has moved out of range
-          npair += __popcll(inm);
-          const bool inr = __builtin_amdgcn_inverse_ballot_w64(inm);
-          PairCore<R, SW> pc;
-          pc.eval(r2, inr, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P);
-          const R u = pc.lj0 * pc.S + pc.el;
-          const R fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
-          const R fs = inr ? fr * pc.rinv2 : R(0);
-          eent += inr ? u : R(0);
-          const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
-          fjx += fx;
-          fjy += fy;
-          fjz += fz;
-          fix[c] -= fx;
-          fiy[c] -= fy;
-          fiz[c] -= fz;
+      for (int c = 0; c < kScCl; ++c) fix[c] = fiy[c] = fiz[c] = R(0);
+    }
+    for (unsigned long long ab = alch_bits; ab; ab &= ab - 1) {
+      const int k = __builtin_ctzll(ab) >> 3;
+      const int e = U.y + k;
+      const uint32_t info = einfo[e];
+      const uint32_t imask = info & 0xffu;
+      const int jsl = jslb[k * kCl + jl];
+      const int code = (int)((info >> 16) & 31u);
+      const int sj = jsl >> 6;
+      const double odx = d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
+      const double ody = d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
+      const double odz = d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
+      const double4 pj64 = pos64[jsl];
+      const double xj = pj64.x + odx, yj = pj64.y + ody, zj = pj64.z + odz;
+      const int tj = d.slot_type[jsl];
+      R fjx = R(0), fjy = R(0), fjz = R(0);
+      double a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll 1
+      for (int c = 0; c < kScCl; ++c) {
+        if (!(imask & (1u << c))) continue;
+        const int isl = s * kSc + c * kCl + il;
+        const double4 pi64 = pos64[isl];
+        const R dx = (R)(xj - pi64.x), dy = (R)(yj - pi64.y), dz = (R)(zj - pi64.z);
+        const P4 tp = tpair[d.slot_type[isl] * T + tj];
+        R u, fr, rinv2;
+        bool inr;
+        const bool valid = __builtin_amdgcn_inverse_ballot_w64(emask[(size_t)e * kScCl + c]);
+        alch_pair<R, SCHED, SW>(dx, dy, dz, valid, tp, la0, la1, P, u, fr, rinv2, inr, a0, a1, a2);
+        npair += __popcll(__ballot(inr));
+        const R fs = inr ? fr * rinv2 : R(0);
+        const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
+        fjx += fx;
+        fjy += fy;
+        fjz += fz;
+        const R gx = red_jl(fx), gy = red_jl(fy), gz = red_jl(fz);
+        if (jl == 0) {
+          fia[c * kCl + il] -= gx;
+          fia[kSc + c * kCl + il] -= gy;
+          fia[2 * kSc + c * kCl + il] -= gz;
         }
       }
       fjx = red8(fjx);
@@ -499,14 +607,11 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
         v.z = fjz;
         v.w = R(0);
         jf[k * kCl + jl] = v;
-        jslb[k * kCl + jl] = jsl;
       }
-      if (kind == KIND_SOLV) {
-        acc_solv += (double)eent;
-      } else if (kind == KIND_SOLU) {
-        *rare0 += (double)eent;
-        rare = true;
-      }
+      *rare1 += a0;
+      *rare2 += a1;
+      *rare3 += a2;
+      rare = true;
     }
     // j-forces parked by the entries of this unit
     wave_sync();
