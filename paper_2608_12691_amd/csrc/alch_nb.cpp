@@ -65,6 +65,7 @@ struct alch_nb_ctx {
   std::vector<GridInfo> grids;
   std::vector<float4> tp32;
   std::vector<double4> tp64;
+  std::vector<float4> dsf32;
   std::vector<ReplicaInfo> reps;
   std::vector<double> sc_box;  // [SC*4]
   int sc_cap = 0, ent_cap = 0, unit_cap = 0;
@@ -181,6 +182,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->last_dudl = cv.take<double>(base, K);
   d->pgrad_part = cv.take<double>(base, (size_t)kPgBlocks * 3 * ctx->T);
   d->tp32 = cv.take<float4>(base, (size_t)ctx->T * ctx->T);
+  d->dsf32 = cv.take<float4>(base, kDsfEntries);
   d->tp64 = cv.take<double4>(base, (size_t)ctx->T * ctx->T);
   ctx->export_counter = cv.take<unsigned long long>(base, 1);
   ctx->ws_bytes = cv.off + 256;
@@ -441,6 +443,26 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
   pc.c2a = 2.0 * p.dsf_alpha / std::sqrt(M_PI);
   pc.B = ec / (p.cutoff * p.cutoff) + pc.c2a * std::exp(-p.dsf_alpha * p.dsf_alpha * p.cutoff * p.cutoff) / p.cutoff;
   pc.sc_alpha = p.sc_alpha;
+  // intervals per unit of r: the largest power of two with rc * inv_h <= kDsfN,
+  // so that r * inv_h and its fraction are exact in FP32
+  pc.inv_h = std::exp2(std::floor(std::log2(kDsfN / p.cutoff)));
+  // cubic Hermite pieces of f(r) = erfc(a r) and g(r) = (2a/sqrt(pi)) exp(-a^2 r^2)
+  // (f' = -g, g' = -2 a^2 r g) in t = (r - r0)/h: c0 + t (c1 + t (c2 + t c3))
+  ctx->dsf32.resize(kDsfEntries);
+  {
+    const double a = p.dsf_alpha, h = 1.0 / pc.inv_h;
+    auto f = [&](double r) { return std::erfc(a * r); };
+    auto g = [&](double r) { return pc.c2a * std::exp(-a * a * r * r); };
+    auto piece = [&](double y0, double y1, double d0, double d1) {
+      return make_float4((float)y0, (float)(h * d0), (float)(3.0 * (y1 - y0) - h * (2.0 * d0 + d1)),
+                         (float)(2.0 * (y0 - y1) + h * (d0 + d1)));
+    };
+    for (int i = 0; i <= kDsfN; ++i) {
+      const double r0 = i * h, r1 = r0 + h;
+      ctx->dsf32[2 * i] = piece(f(r0), f(r1), -g(r0), -g(r1));
+      ctx->dsf32[2 * i + 1] = piece(g(r0), g(r1), -2.0 * a * a * r0 * g(r0), -2.0 * a * a * r1 * g(r1));
+    }
+  }
   // type-pair table in FP64: sigma_ij, 4 eps_ij, k_e q_i q_j, 1/sigma_ij^6
   ctx->tp32.resize((size_t)ctx->T * ctx->T);
   ctx->tp64.resize((size_t)ctx->T * ctx->T);
@@ -516,6 +538,7 @@ alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* st
   HIPCHK(up(d.type_q, ctx->charge.data(), sizeof(double) * ctx->T));
   HIPCHK(up(d.col_grid, ctx->col_grid.data(), sizeof(int) * ctx->C));
   HIPCHK(up(d.tp32, ctx->tp32.data(), sizeof(float4) * ctx->tp32.size()));
+  HIPCHK(up(d.dsf32, ctx->dsf32.data(), sizeof(float4) * ctx->dsf32.size()));
   HIPCHK(up(d.tp64, ctx->tp64.data(), sizeof(double4) * ctx->tp64.size()));
   HIPCHK(launch_init(d, st));
   // the host copies must outlive the asynchronous uploads

@@ -140,6 +140,7 @@ struct Dev {
   double* last_dudl;         // [K] dU/dlambda of the last forward
   double* pgrad_part;        // [PG_BLOCKS*3*T] parameter-gradient partials
   const float4* tp32;        // [T*T] type-pair sigma, 4 eps, k_e q q, 1/sigma^6 (rounded from FP64)
+  const float4* dsf32;       // [kDsfEntries] FP32 DSF pieces (erfc, then the Gaussian term, per interval)
   const double4* tp64;       // [T*T]
 };
 

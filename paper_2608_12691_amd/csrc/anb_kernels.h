@@ -11,7 +11,15 @@ struct PotConsts {
   double rc, rc2, rs, inv_w;   // cutoff, its square, switch start, 1/width (0 = no switch)
   double alpha, A, B, c2a;     // DSF: a, erfc(a rc)/rc, slope, 2a/sqrt(pi)
   double sc_alpha;             // Beutler soft-core alpha
+  double inv_h;                // intervals per unit of r in the FP32 DSF table (a power of two)
 };
+
+// The FP32 path reads erfc(a r) and (2a/sqrt(pi)) exp(-a^2 r^2) from cubic
+// Hermite pieces on kDsfN + 1 equal intervals of width 1/inv_h starting at
+// r = 0, with rc * inv_h <= kDsfN; each interval holds two float4 of
+// coefficients in the local variable t in [0, 1].
+constexpr int kDsfN = 256;
+constexpr int kDsfEntries = 2 * (kDsfN + 1);
 
 constexpr int kMaxEpu = 8;  // entries per work unit at most (LDS staging of j-forces)
 

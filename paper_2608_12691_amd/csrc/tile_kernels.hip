@@ -66,7 +66,7 @@ struct C4<double> {
 
 template <typename R>
 struct Pot {
-  R rc2, rc, rs, inv_w, alpha, A, B, c2a, sca;
+  R rc2, rc, rs, inv_w, alpha, A, B, c2a, sca, inv_h;
 };
 
 template <typename R>
@@ -81,19 +81,23 @@ __host__ Pot<R> make_pot(const PotConsts& p) {
   o.B = (R)p.B;
   o.c2a = (R)p.c2a;
   o.sca = (R)p.sc_alpha;
+  o.inv_h = (R)p.inv_h;
   return o;
 }
 
-// Switched LJ, DSF and the scalar pair force.  All lanes compute; lanes
-// outside the cutoff or masked out get r2 := 1 so every value stays finite,
-// and their outputs are selected to zero.
+// Switched LJ, DSF and the scalar pair force.  Lanes outside the cutoff or
+// masked out get r2 := 1 so every value stays finite (callers select their
+// outputs to zero or run the lanes of in-range pairs only).  erfc(a r) and
+// the Gaussian term: in FP32 from the cubic pieces in tab (LDS) when kTable,
+// else from the rational fit; in FP64 from the library functions.
 template <typename R, bool SW>
 struct PairCore {
   R r2s, rinv, rinv2, r;
   R lj0, flj0;   // unswitched LJ and -r dLJ/dr
   R S, rdS;      // switch and r dS/dr
   R el, fel;     // q q D(r) and -r d(q q D)/dr
-  __device__ inline void eval(R r2, bool inr, R sij, R e4, R qq, const Pot<R>& P) {
+  template <bool kTable>
+  __device__ inline void eval(R r2, bool inr, R sij, R e4, R qq, const Pot<R>& P, const float4* tab) {
     r2s = inr ? r2 : R(1);
     rinv = rsq(r2s);
     rinv2 = rinv * rinv;
@@ -112,11 +116,21 @@ struct PairCore {
       S = R(1);
       rdS = R(0);
     }
-    R ec, ex;
-    erfc_exp(P.alpha * r, ec, ex);
+    R ec, gx;
+    if constexpr (sizeof(R) == 4 && kTable) {
+      const float u = r * P.inv_h;  // exact; 0 <= u <= kDsfN for r <= rc
+      const float4 fa = tab[2 * (int)u], fb = tab[2 * (int)u + 1];
+      const float t = __builtin_amdgcn_fractf(u);
+      ec = fmaf(fmaf(fmaf(fa.w, t, fa.z), t, fa.y), t, fa.x);
+      gx = fmaf(fmaf(fmaf(fb.w, t, fb.z), t, fb.y), t, fb.x);
+    } else {
+      R ex;
+      erfc_exp(P.alpha * r, ec, ex);
+      gx = P.c2a * ex;
+    }
     const R erinv = ec * rinv;
     el = qq * (erinv - P.A + P.B * (r - P.rc));
-    fel = qq * (erinv + P.c2a * ex - P.B * r);
+    fel = qq * (erinv + gx - P.B * r);
   }
 };
 
@@ -281,13 +295,15 @@ __device__ inline double local_coord(const Dev& d, const double* __restrict__ x,
 // lambda derivative, a sum with cancellation, at FP32 rounding level.
 template <typename R, int SCHED, bool SW>
 __device__ inline void alch_pair(R dx, R dy, R dz, bool valid, const typename C4<R>::P4& tp, R lv_or_hA, R le_or_hB,
-                                 const Pot<R>& P, R& u, R& fr, R& rinv2, bool& inr, double& a0, double& a1,
-                                 double& a2) {
+                                 const Pot<R>& P, const float4* tab, R& u, R& fr, R& rinv2, bool& inr,
+                                 double& a0, double& a1, double& a2) {
   const R r2 = dx * dx + dy * dy + dz * dz;
   inr = valid && r2 < P.rc2;
   const R sij = tp.x, e4 = tp.y, qq = tp.z, inv_s6 = tp.w;
+  // the rational fit here: dU/dlambda is a sum with cancellation over these
+  // pairs, and they are few
   PairCore<R, SW> pc;
-  pc.eval(r2, inr, sij, e4, qq, P);
+  pc.template eval<false>(r2, inr, sij, e4, qq, P, tab);
   rinv2 = pc.rinv2;
   if (SCHED == 0) {
     // Beutler soft core: lv 4eps (x^2 - x) S + le qq D
@@ -372,6 +388,12 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   __shared__ R fia_all[kBlk / 64][3][kSc];
   R* fia = &fia_all[threadIdx.x >> 6][0][0];
   const int il = lane & 7, jl = lane >> 3;
+  // FP32 DSF pieces, once per block
+  __shared__ float4 dsf[sizeof(R) == 4 ? kDsfEntries : 1];
+  if (sizeof(R) == 4) {
+    for (int i = threadIdx.x; i < kDsfEntries; i += kBlk) dsf[i] = d.dsf32[i];
+    __syncthreads();
+  }
   const int n_units = d.ctr[CTR_NUNIT];
   // Unit range of this wave: equal runs of units (the unit cuts already cap
   // each unit's tiles).  The wave index is made provably uniform: unit and
@@ -509,20 +531,22 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
         const unsigned long long inm = __ballot(r2 < P.rc2) & mcur[c];
         if (inm == 0) continue;  // the whole 64-pair tile has moved out of range
         npair += __popcll(inm);
-        const bool inr = __builtin_amdgcn_inverse_ballot_w64(inm);
-        PairCore<R, SW> pc;
-        pc.eval(r2, inr, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P);
-        const R u = pc.lj0 * pc.S + pc.el;
-        const R fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
-        const R fs = inr ? fr * pc.rinv2 : R(0);
-        eent += inr ? u : R(0);
-        const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
-        fjx += fx;
-        fjy += fy;
-        fjz += fz;
-        fix[c] -= fx;
-        fiy[c] -= fy;
-        fiz[c] -= fz;
+        // only the lanes of in-range pairs execute the pair math
+        if (__builtin_amdgcn_inverse_ballot_w64(inm)) {
+          PairCore<R, SW> pc;
+          pc.template eval<true>(r2, true, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P, dsf);
+          const R u = pc.lj0 * pc.S + pc.el;
+          const R fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
+          const R fs = fr * pc.rinv2;
+          eent += u;
+          const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
+          fjx += fx;
+          fjy += fy;
+          fjz += fz;
+          fix[c] -= fx;
+          fiy[c] -= fy;
+          fiz[c] -= fz;
+        }
       }
       fjx = red8(fjx);
       fjy = red8(fjy);
@@ -583,7 +607,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
         R u, fr, rinv2;
         bool inr;
         const bool valid = __builtin_amdgcn_inverse_ballot_w64(emask[(size_t)e * kScCl + c]);
-        alch_pair<R, SCHED, SW>(dx, dy, dz, valid, tp, la0, la1, P, u, fr, rinv2, inr, a0, a1, a2);
+        alch_pair<R, SCHED, SW>(dx, dy, dz, valid, tp, la0, la1, P, dsf, u, fr, rinv2, inr, a0, a1, a2);
         npair += __popcll(__ballot(inr));
         const R fs = inr ? fr * rinv2 : R(0);
         const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
