@@ -166,6 +166,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->ent_info = cv.take<uint32_t>(base, E);
   d->ent_isc = cv.take<int>(base, E);
   d->ent_mask = cv.take<unsigned long long>(base, E * kScCl);
+  d->ent_off = cv.take<double4>(base, E);
   d->units = cv.take<int4>(base, U);
   d->rep_ustart = cv.take<int>(base, K + 1);
   d->ctr = cv.take<int>(base, 16);

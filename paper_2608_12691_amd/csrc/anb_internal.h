@@ -121,6 +121,7 @@ struct Dev {
   int* sc_ustart;            // [SC]
   int* ent_jc;               // [E]
   uint32_t* ent_info;        // [E]
+  double4* ent_off;          // [E] offset of the entry's j-cluster image from its i-SC origin (FP64, set with the masks)
   int* ent_isc;              // [E]
   unsigned long long* ent_mask;  // [E*8]
   int4* units;               // [U] sc, e0, e1, replica

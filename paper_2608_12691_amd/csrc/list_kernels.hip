@@ -647,6 +647,13 @@ __device__ void ph_masks(const Dev& d, double rl2) {
       if (lane == c) mine = M;
     }
     if (lane < kScCl) d.ent_mask[(size_t)e * kScCl + lane] = mine;
+    if (lane == 0) {
+      // the tile kernel adds this to the j-cluster's local coordinates
+      const int sj = jc >> 3;
+      d.ent_off[e] = make_double4(d.sc_origin[3 * sj] + shx - d.sc_origin[3 * s],
+                                  d.sc_origin[3 * sj + 1] + shy - d.sc_origin[3 * s + 1],
+                                  d.sc_origin[3 * sj + 2] + shz - d.sc_origin[3 * s + 2], 0.0);
+    }
     if (lane == 0 && keep != imask) d.ent_info[e] = (info & ~0xffu) | keep;
     tiles += __popc(keep);
   }

@@ -419,12 +419,49 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     add_fixed_lanes(d.ffix + slots + sl, gy, fscale, d.flags, true);
     add_fixed_lanes(d.ffix + 2 * slots + sl, gz, fscale, d.flags, true);
   };
+  // Unit headers of this wave, lane i holding unit ub + 64 m + i (vector
+  // loads, read back with lane reads), and the per-lane entry data of the
+  // next unit loaded one unit ahead: lane (k, t) takes entry U.y + k.
+  int4 hdr = make_int4(0, 0, 0, 0);
+  auto load_hdrs = [&](int base) {
+    const int u = base + lane;
+    if (u < ue) hdr = d.units[u];
+  };
+  auto header = [&](int u) {
+    const int i = (u - ub) & 63;
+    return make_int4(__builtin_amdgcn_readlane(hdr.x, i), __builtin_amdgcn_readlane(hdr.y, i),
+                     __builtin_amdgcn_readlane(hdr.z, i), __builtin_amdgcn_readlane(hdr.w, i));
+  };
+  int n_jc = 0;
+  uint32_t n_inf = 0;
+  double4 n_off = make_double4(0.0, 0.0, 0.0, 0.0);
+  auto load_entries = [&](const int4& V) {
+    const int e = V.y + (lane >> 3);
+    n_jc = 0;
+    n_inf = 0;
+    n_off = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (e < V.z) {
+      n_jc = d.ent_jc[e];
+      n_inf = d.ent_info[e];
+      n_off = d.ent_off[e];
+    }
+  };
+  bool have_next = false;
+  if (ub < ue) {
+    load_hdrs(ub);
+    load_entries(header(ub));
+    have_next = true;
+  }
   for (int u = ub; u < ue; ++u) {
-    const cptr<int> up = as_const(reinterpret_cast<const int*>(d.units)) + 4 * u;
-    const int4 U = make_int4(up[0], up[1], up[2], up[3]);
+    if (u > ub && ((u - ub) & 63) == 0) load_hdrs(u);  // past 64 units (large boxes)
+    const int4 U = header(u);
+    if (!have_next) load_entries(U);
+    const int c_jc = n_jc;
+    const uint32_t c_inf = n_inf;
+    const double4 c_off = n_off;
+    have_next = u + 1 < ue && ((u + 1 - ub) & 63) != 0;
+    if (have_next) load_entries(header(u + 1));
     const int s = U.x;
-    const ReplicaInfo& rp = d.reps[U.w];
-    const double L0 = rp.box[0], L1 = rp.box[1], L2 = rp.box[2];
     const LamState lam = d.lam[U.w];
     R la0, la1;
     if (sizeof(R) == 4) {
@@ -447,8 +484,6 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       for (int c = 0; c < kScCl; ++c) fix[c] = fiy[c] = fiz[c] = R(0);
       cur_s = s;
     }
-    const double ox0 = as_const(d.sc_origin)[3 * s], oy0 = as_const(d.sc_origin)[3 * s + 1],
-                 oz0 = as_const(d.sc_origin)[3 * s + 2];
     double acc_solv = 0;
     bool rare = false;  // wave-uniform: the unit had a solute-solute or solute-solvent entry
     *rare0 = *rare1 = *rare2 = *rare3 = 0.0;
@@ -463,22 +498,15 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       v.x = v.y = v.z = v.w = R(0);
       q.x = q.y = R(0);
       int jsl = 0;
-      uint32_t inf = 0;
+      const uint32_t inf = c_inf;
       if (e < U.z) {
-        const int jc = d.ent_jc[e];
-        inf = d.ent_info[e];
-        const int code = (int)((inf >> 16) & 31u);
-        const int sj = jc >> 3;
-        jsl = jc * kCl + t;
+        jsl = c_jc * kCl + t;
         v = pos[jsl];
         q = se[jsl];
         // offset of the j-cluster's image from the i-super-cluster origin
-        const double odx = d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
-        const double ody = d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
-        const double odz = d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
-        v.x += (R)odx;
-        v.y += (R)ody;
-        v.z += (R)odz;
+        v.x += (R)c_off.x;
+        v.y += (R)c_off.y;
+        v.z += (R)c_off.z;
       }
       wave_sync();
       jpos[lane] = v;
@@ -587,13 +615,9 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       const uint32_t info = einfo[e];
       const uint32_t imask = info & 0xffu;
       const int jsl = jslb[k * kCl + jl];
-      const int code = (int)((info >> 16) & 31u);
-      const int sj = jsl >> 6;
-      const double odx = d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - ox0;
-      const double ody = d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - oy0;
-      const double odz = d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - oz0;
+      const double4 off = d.ent_off[e];
       const double4 pj64 = pos64[jsl];
-      const double xj = pj64.x + odx, yj = pj64.y + ody, zj = pj64.z + odz;
+      const double xj = pj64.x + off.x, yj = pj64.y + off.y, zj = pj64.z + off.z;
       const int tj = d.slot_type[jsl];
       R fjx = R(0), fjy = R(0), fjz = R(0);
       double a0 = 0, a1 = 0, a2 = 0;
@@ -866,18 +890,24 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
     return;
   }
   if (!forces) return;
-  // one force component per thread
+  // one slot per thread: its three sums and its atom index are independent loads
   const int slots = d.sc_cap * kSc;
-  const int n3 = 3 * d.n_atoms;
-  for (int i = (blockIdx.x - nred) * blockDim.x + threadIdx.x; i < n3; i += (gridDim.x - nred) * blockDim.x) {
-    const int a = i / 3, c = i - 3 * a;
-    forces[i] = (double)(long long)d.ffix[c * slots + d.atom_slot[a]] * inv_scale;
+  for (int sl = (blockIdx.x - nred) * blockDim.x + threadIdx.x; sl < slots; sl += (gridDim.x - nred) * blockDim.x) {
+    const int a = d.slot_atom[sl];
+    const long long fx = (long long)d.ffix[sl];
+    const long long fy = (long long)d.ffix[slots + sl];
+    const long long fz = (long long)d.ffix[2 * slots + sl];
+    if (a >= 0) {
+      forces[3 * a] = (double)fx * inv_scale;
+      forces[3 * a + 1] = (double)fy * inv_scale;
+      forces[3 * a + 2] = (double)fz * inv_scale;
+    }
   }
 }
 
 hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int schedule, double* terms, double* forces,
                            double* dudl, long long* n_pairs) {
-  const int gf = forces ? max(1, min(2048, (3 * d.n_atoms + kBlk - 1) / kBlk)) : 0;
+  const int gf = forces ? max(1, min(2048, (d.sc_cap * kSc + kBlk - 1) / kBlk)) : 0;
   hipLaunchKernelGGL(k_finalize, dim3(d.n_reps * kRedChunks + gf), dim3(kBlk), 0, st, d, schedule,
                      1.0 / fixed_scale(precision),
                      terms, forces, dudl, n_pairs);
