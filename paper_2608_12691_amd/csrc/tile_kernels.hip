@@ -396,39 +396,62 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   }
   const int n_units = d.ctr[CTR_NUNIT];
   // Unit range of this wave: equal runs of units (the unit cuts already cap
-  // each unit's tiles).  The wave index is made provably uniform: unit and
-  // entry indices then live in scalar registers and their loads are scalar.
+  // each unit's tiles; runs keep a super-cluster's units on one wave).  The
+  // wave index is made provably uniform: unit and entry indices then live in
+  // scalar registers.
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = gridDim.x * (kBlk / 64), w = blockIdx.x * (kBlk / 64) + wib;
   const int ub = (int)((long long)n_units * w / nw);
-  const int ue = (int)((long long)n_units * (w + 1) / nw);
+  const int nr = (int)((long long)n_units * (w + 1) / nw) - ub;
   // i-forces of the current super-cluster, carried over consecutive units
   // of the same super-cluster; they leave when it changes: summed over jl,
   // lane (jl, il) then takes i-cluster c = jl so that lane l holds slot
   // s * 64 + l, and three 64-lane atomics write them
   R fix[kScCl], fiy[kScCl], fiz[kScCl];
   int cur_s = -1;
-  auto flush_i = [&](int sc) {
+  // Force atomics wait: the j-forces of a unit and the i-forces of a
+  // finished super-cluster are issued after the next unit's loads, so that
+  // those loads do not queue behind them.
+  P4 pj;  // pending j-forces (lane l: slot pj_sl of entry l / 8)
+  int pj_sl = 0;
+  bool pj_have = false;
+  R pi_x = R(0), pi_y = R(0), pi_z = R(0);  // pending i-forces of super-cluster pi_s
+  int pi_s = -1;
+  auto reduce_i = [&]() {
     const bool odd8 = (lane & 8) != 0;
     wave_sync();
-    R gx = scatter_jl(fix, odd8) + fia[lane];
-    R gy = scatter_jl(fiy, odd8) + fia[kSc + lane];
-    R gz = scatter_jl(fiz, odd8) + fia[2 * kSc + lane];
-    const int sl = sc * kSc + lane;
-    add_fixed_lanes(d.ffix + sl, gx, fscale, d.flags, true);
-    add_fixed_lanes(d.ffix + slots + sl, gy, fscale, d.flags, true);
-    add_fixed_lanes(d.ffix + 2 * slots + sl, gz, fscale, d.flags, true);
+    pi_x = scatter_jl(fix, odd8) + fia[lane];
+    pi_y = scatter_jl(fiy, odd8) + fia[kSc + lane];
+    pi_z = scatter_jl(fiz, odd8) + fia[2 * kSc + lane];
+    pi_s = cur_s;
+  };
+  auto put_pending = [&]() {
+    if (pj_have) {
+      const bool on = pj_sl >= 0;
+      const int sl = on ? pj_sl : 0;
+      add_fixed_lanes(d.ffix + sl, pj.x, fscale, d.flags, on);
+      add_fixed_lanes(d.ffix + slots + sl, pj.y, fscale, d.flags, on);
+      add_fixed_lanes(d.ffix + 2 * slots + sl, pj.z, fscale, d.flags, on);
+      pj_have = false;
+    }
+    if (pi_s >= 0) {
+      const int sl = pi_s * kSc + lane;
+      add_fixed_lanes(d.ffix + sl, pi_x, fscale, d.flags, true);
+      add_fixed_lanes(d.ffix + slots + sl, pi_y, fscale, d.flags, true);
+      add_fixed_lanes(d.ffix + 2 * slots + sl, pi_z, fscale, d.flags, true);
+      pi_s = -1;
+    }
   };
   // Unit headers of this wave, lane i holding unit ub + 64 m + i (vector
   // loads, read back with lane reads), and the per-lane entry data of the
   // next unit loaded one unit ahead: lane (k, t) takes entry U.y + k.
   int4 hdr = make_int4(0, 0, 0, 0);
   auto load_hdrs = [&](int base) {
-    const int u = base + lane;
-    if (u < ue) hdr = d.units[u];
+    const int r = base + lane;
+    if (r < nr) hdr = d.units[ub + r];
   };
-  auto header = [&](int u) {
-    const int i = (u - ub) & 63;
+  auto header = [&](int r) {
+    const int i = r & 63;
     return make_int4(__builtin_amdgcn_readlane(hdr.x, i), __builtin_amdgcn_readlane(hdr.y, i),
                      __builtin_amdgcn_readlane(hdr.z, i), __builtin_amdgcn_readlane(hdr.w, i));
   };
@@ -447,20 +470,21 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     }
   };
   bool have_next = false;
-  if (ub < ue) {
-    load_hdrs(ub);
-    load_entries(header(ub));
+  if (nr > 0) {
+    load_hdrs(0);
+    load_entries(header(0));
     have_next = true;
   }
-  for (int u = ub; u < ue; ++u) {
-    if (u > ub && ((u - ub) & 63) == 0) load_hdrs(u);  // past 64 units (large boxes)
-    const int4 U = header(u);
+  for (int r = 0; r < nr; ++r) {
+    if (r > 0 && (r & 63) == 0) load_hdrs(r);  // past 64 units (large boxes)
+    const int4 U = header(r);
+    const int u = ub + r;
     if (!have_next) load_entries(U);
     const int c_jc = n_jc;
     const uint32_t c_inf = n_inf;
     const double4 c_off = n_off;
-    have_next = u + 1 < ue && ((u + 1 - ub) & 63) != 0;
-    if (have_next) load_entries(header(u + 1));
+    have_next = r + 1 < nr && ((r + 1) & 63) != 0;
+    if (have_next) load_entries(header(r + 1));
     const int s = U.x;
     const LamState lam = d.lam[U.w];
     R la0, la1;
@@ -471,18 +495,14 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       la0 = (R)lam.a[0];
       la1 = (R)lam.a[1];
     }
-    if (s != cur_s) {
-      if (cur_s >= 0) flush_i(cur_s);
-      // the super-cluster's 64 atoms go to this wave's LDS slice (lane l
-      // holds slot l); lane (jl, il) then reads atom c*8 + il of i-cluster c
-      wave_sync();
-      ipos[lane] = pos[s * kSc + lane];
-      ise[lane] = se[s * kSc + lane];
-      fia[lane] = fia[kSc + lane] = fia[2 * kSc + lane] = R(0);
-      wave_sync();
-#pragma unroll
-      for (int c = 0; c < kScCl; ++c) fix[c] = fiy[c] = fiz[c] = R(0);
-      cur_s = s;
+    const bool new_s = s != cur_s;
+    P4 ip;
+    P2 iq;
+    if (new_s) {
+      if (cur_s >= 0) reduce_i();
+      // the super-cluster's 64 atoms (lane l: slot l)
+      ip = pos[s * kSc + lane];
+      iq = se[s * kSc + lane];
     }
     double acc_solv = 0;
     bool rare = false;  // wave-uniform: the unit had a solute-solute or solute-solvent entry
@@ -503,12 +523,22 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
         jsl = c_jc * kCl + t;
         v = pos[jsl];
         q = se[jsl];
-        // offset of the j-cluster's image from the i-super-cluster origin
-        v.x += (R)c_off.x;
-        v.y += (R)c_off.y;
-        v.z += (R)c_off.z;
       }
+      put_pending();
+      // offset of the j-cluster's image from the i-super-cluster origin
+      v.x += (R)c_off.x;
+      v.y += (R)c_off.y;
+      v.z += (R)c_off.z;
       wave_sync();
+      if (new_s) {
+        // lane (jl, il) then reads atom c*8 + il of i-cluster c
+        ipos[lane] = ip;
+        ise[lane] = iq;
+        fia[lane] = fia[kSc + lane] = fia[2 * kSc + lane] = R(0);
+#pragma unroll
+        for (int c = 0; c < kScCl; ++c) fix[c] = fiy[c] = fiz[c] = R(0);
+        cur_s = s;
+      }
       jpos[lane] = v;
       jse[lane] = q;
       jslb[lane] = jsl;
@@ -661,20 +691,17 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       *rare3 += a2;
       rare = true;
     }
-    // j-forces parked by the entries of this unit
+    // j-forces parked by the entries of this unit, to registers
     wave_sync();
     {
       const bool have = lane < (U.z - U.y) * kCl;
-      P4 v;
-      v.x = v.y = v.z = v.w = R(0);
-      int sl = 0;
+      pj.x = pj.y = pj.z = pj.w = R(0);
+      pj_sl = -1;
       if (have) {
-        v = jf[lane];
-        sl = jslb[lane];
+        pj = jf[lane];
+        pj_sl = jslb[lane];
       }
-      add_fixed_lanes(d.ffix + sl, v.x, fscale, d.flags, have);
-      add_fixed_lanes(d.ffix + slots + sl, v.y, fscale, d.flags, have);
-      add_fixed_lanes(d.ffix + 2 * slots + sl, v.z, fscale, d.flags, have);
+      pj_have = true;
     }
     wave_sync();
     acc_solv = wave_sum(acc_solv);
@@ -696,7 +723,8 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       o[ACC_NPAIR * U] = (double)npair;
     }
   }
-  if (cur_s >= 0) flush_i(cur_s);
+  if (cur_s >= 0) reduce_i();
+  put_pending();
 }
 
 hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
