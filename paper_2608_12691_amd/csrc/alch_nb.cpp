@@ -150,6 +150,8 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->cl_n = cv.take<int>(base, CL);
   d->slot_atom = cv.take<int>(base, SL);
   d->atom_slot = cv.take<int>(base, N);
+  d->atom_off = cv.take<double4>(base, N);
+  d->atom_box = cv.take<double4>(base, N);
   d->slot_xw = cv.take<double4>(base, SL);
   d->slot_comp = cv.take<int>(base, SL);
   d->slot_type = cv.take<int>(base, SL);

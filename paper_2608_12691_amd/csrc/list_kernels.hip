@@ -352,8 +352,12 @@ __device__ void ph_build_sc(const Dev& d) {
     // this list (the positions are those of the build), and cleared force
     // accumulators; later calls refresh them in the prepare pass
     double q[3] = {0.0, 0.0, 0.0};
-    if (v)
+    if (v) {
       for (int k = 0; k < 3; ++k) q[k] = w[k] - org[k];
+      // what the per-call pass adds to the displacement since the build
+      d.atom_off[a] = make_double4(q[0], q[1], q[2], 0.0);
+      d.atom_box[a] = d.sc_box[s];
+    }
     d.pos32[sl] = make_float4((float)q[0], (float)q[1], (float)q[2], d.q32[sl]);
     d.pos64[sl] = make_double4(q[0], q[1], q[2], d.q64[sl]);
     const int slots = d.sc_cap * kSc;

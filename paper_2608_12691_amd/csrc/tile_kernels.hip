@@ -818,23 +818,31 @@ __global__ void __launch_bounds__(kBlk) k_prepare(Dev d, const double* __restric
     const double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
     if (!(isfinite(x) && isfinite(y) && isfinite(z))) bad = true;  // reported; the values still flow
     if (!have_list || mode == 2) continue;  // the list build writes the slot data
-    const ReplicaInfo& rp = d.reps[d.atom_rep[a]];
+    // per-atom records written with the slots: every load here is
+    // independent of the others
+    const double4 L = d.atom_box[a], off = d.atom_off[a];
+    const int sl = d.atom_slot[a];
+    const double Lk[3] = {L.x, L.y, L.z}, ok[3] = {off.x, off.y, off.z};
     double dd[3] = {x - d.x_build[3 * a], y - d.x_build[3 * a + 1], z - d.x_build[3 * a + 2]};
     double r2 = 0;
     for (int k = 0; k < 3; ++k) {
-      dd[k] -= rp.box[k] * rint(dd[k] / rp.box[k]);
+      dd[k] -= Lk[k] * rint(dd[k] / Lk[k]);
       r2 += dd[k] * dd[k];
     }
     if (r2 > half_skin2) moved = true;
     // Coordinates relative to the atom's SC origin in the image it had at
     // the build (displacement since the build plus the build-time offset),
-    // and cleared force accumulators.  If this call rebuilds the list, the
-    // build overwrites them for the new slots.
-    const int sl = d.atom_slot[a], s = sl / kSc;
+    // and cleared force accumulators; the charges in .w stay from the
+    // build.  If this call rebuilds the list, the build overwrites them for
+    // the new slots.
     double q[3];
-    for (int k = 0; k < 3; ++k) q[k] = dd[k] + (d.xw[3 * a + k] - d.sc_origin[3 * s + k]);
-    d.pos32[sl] = make_float4((float)q[0], (float)q[1], (float)q[2], d.q32[sl]);
-    d.pos64[sl] = make_double4(q[0], q[1], q[2], d.q64[sl]);
+    for (int k = 0; k < 3; ++k) q[k] = dd[k] + ok[k];
+    float* p32 = reinterpret_cast<float*>(d.pos32 + sl);
+    double* p64 = reinterpret_cast<double*>(d.pos64 + sl);
+    for (int k = 0; k < 3; ++k) {
+      p32[k] = (float)q[k];
+      p64[k] = q[k];
+    }
     const int slots = d.sc_cap * kSc;
     d.ffix[sl] = 0ull;
     d.ffix[slots + sl] = 0ull;
