@@ -227,3 +227,49 @@ def test_config4_batched_replicas(precision):
                          w.lambdas[k:k + 1], w.seed)
         compare(sub, [ref], one, [w.systems[k].positions], precision, np.array([0, off[k + 1] - off[k]]),
                 label="cfg4 box %d" % k)
+
+
+def _squeezed_waters(w, d_oo):
+    """Config 1 with one water moved rigidly so that its oxygen sits d_oo from
+    another water's oxygen (every other atom pair stays >= 0.9 A apart)."""
+    s = w.systems[0]
+    x = s.positions.copy()
+    L = s.box
+    first = int(np.nonzero(s.is_solute == 0)[0][0])
+    oxy = np.arange(first, s.n_atoms, 3)
+    for a in oxy[:40]:
+        for b in oxy:
+            if b == a:
+                continue
+            v = x[b] - x[a]
+            v -= L * np.rint(v / L)
+            y = x.copy()
+            y[b:b + 3] += (v / np.linalg.norm(v)) * d_oo - v
+            dmin = np.inf
+            for m in range(b, b + 3):
+                dv = y - y[m]
+                dv -= L * np.rint(dv / L)
+                r = np.sqrt((dv * dv).sum(1))
+                r[b:b + 3] = np.inf
+                r[a] = np.inf if m == b else r[a]
+                dmin = min(dmin, r.min())
+            if dmin >= 0.9:
+                return y, a, b
+    raise AssertionError("no water pair to squeeze")
+
+
+@pytest.mark.parametrize("precision", [1, 0], ids=["fp64", "fp32"])
+def test_large_pair_forces_fixed_point(precision):
+    """An O-O contact at 1.2 A gives pair forces of ~6e5 kcal/mol/A: above
+    2^51 fixed-point units in both precisions (the general conversion path of
+    the force sums) and below the overflow limit (2^62 units)."""
+    w = workload(1)
+    y, a, b = _squeezed_waters(w, 1.2)
+    ref = oracle_for(w, 0, 0.5, O.BEUTLER, positions=y)
+    fmax = np.abs(ref["forces"]).max()
+    scale = 2.0 ** 40 if precision == 1 else 2.0 ** 32
+    assert 2.0 ** 51 < fmax * scale < 2.0 ** 62, fmax
+    ctx = _ctx(w, precision)
+    res, pos = _run(ctx, w, [0.5], positions=[y], flags=2)
+    assert res["flags"] == 0
+    compare(res, [ref], w, pos, precision, _offsets(w), label="squeezed O-O")
