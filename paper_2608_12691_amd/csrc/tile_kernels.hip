@@ -411,7 +411,9 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   int cur_s = -1;
   // Force atomics wait: the j-forces of a unit and the i-forces of a
   // finished super-cluster are issued after the next unit's loads, so that
-  // those loads do not queue behind them.
+  // those loads do not queue behind them (FP32; the FP64 kernel, at its
+  // register limit, issues them at once).
+  constexpr bool kDefer = sizeof(R) == 4;
   P4 pj;  // pending j-forces (lane l: slot pj_sl of entry l / 8)
   int pj_sl = 0;
   bool pj_have = false;
@@ -499,10 +501,24 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     P4 ip;
     P2 iq;
     if (new_s) {
-      if (cur_s >= 0) reduce_i();
+      if (cur_s >= 0) {
+        reduce_i();
+        if (!kDefer) put_pending();
+      }
       // the super-cluster's 64 atoms (lane l: slot l)
       ip = pos[s * kSc + lane];
       iq = se[s * kSc + lane];
+      if (!kDefer) {
+        // straight to LDS: the FP64 kernel holds no extra registers here
+        wave_sync();
+        ipos[lane] = ip;
+        ise[lane] = iq;
+        fia[lane] = fia[kSc + lane] = fia[2 * kSc + lane] = R(0);
+#pragma unroll
+        for (int c = 0; c < kScCl; ++c) fix[c] = fiy[c] = fiz[c] = R(0);
+        cur_s = s;
+        wave_sync();
+      }
     }
     double acc_solv = 0;
     bool rare = false;  // wave-uniform: the unit had a solute-solute or solute-solvent entry
@@ -530,7 +546,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       v.y += (R)c_off.y;
       v.z += (R)c_off.z;
       wave_sync();
-      if (new_s) {
+      if (kDefer && new_s) {
         // lane (jl, il) then reads atom c*8 + il of i-cluster c
         ipos[lane] = ip;
         ise[lane] = iq;
@@ -702,6 +718,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
         pj_sl = jslb[lane];
       }
       pj_have = true;
+      if (!kDefer) put_pending();
     }
     wave_sync();
     acc_solv = wave_sum(acc_solv);
