@@ -278,16 +278,6 @@ __device__ inline void add_fixed_lanes(unsigned long long* p, R v, double scale,
 
 // ------------------------------------------------------------ tile kernel
 
-// Coordinate k of atom a relative to the origin of its super-cluster s, in
-// the periodic image the atom had when the list was built: the displacement
-// since the build (minimum image) plus the build-time wrapped offset.  This
-// stays consistent with the list's image shifts for any super-cluster extent.
-__device__ inline double local_coord(const Dev& d, const double* __restrict__ x, int a, int s, int k, double L) {
-  double m = x[3 * a + k] - d.x_build[3 * a + k];
-  m -= L * rint(m / L);
-  return m + (d.xw[3 * a + k] - d.sc_origin[3 * s + k]);
-}
-
 // Solute-solvent pair (rare: only entries of kind KIND_ALCH).  Its inputs
 // are taken from FP64 sources and rounded once: the displacement from the
 // FP64 positions (minimum image), and sigma_ij, 4 eps_ij, k_e q_i q_j and
