@@ -232,9 +232,29 @@ __device__ inline R scatter_jl(R (&in)[8], bool odd8) {
   return keep + ror8(send);
 }
 
+// Sum over the wave, the same value in every lane: within rows of 16 by DPP
+// lane moves (pairs, quads, mirrored halves, mirrored rows), then across
+// rows with the lane-swap instructions; each step adds two equal partial
+// sums, so every lane ends with the same bits.
+template <int kCtrl>
+__device__ inline double dpp64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), kCtrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), kCtrl, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ inline double wave_sum(double v) {
-  for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dpp64<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp64<0x141>(v);  // row_half_mirror
+  v += dpp64<0x140>(v);  // row_mirror
+  double a = v, b = v;
+  swap16(a, b);
+  v = a + b;
+  a = v;
+  b = v;
+  swap32(a, b);
+  return a + b;
 }
 
 // Read-only view of list data inside the tile kernel: the constant address
