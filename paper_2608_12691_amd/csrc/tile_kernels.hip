@@ -891,14 +891,15 @@ hipError_t launch_prepare(const Dev& d, hipStream_t st, const double* pos, const
 
 
 // Blocks [0, K * kRedChunks): block (k, c) sums chunk c of box k's unit
-// partials (fixed chunk bounds and tree order); the last chunk of box k to
+// partials (fixed chunk bounds; strided per-thread sums, a butterfly per
+// wave, the waves in order); the last chunk of box k to
 // finish (counter red_done[k]) adds the kRedChunks chunk sums in order and
 // writes the energy terms.  Blocks beyond: fixed-point forces -> float64 in
 // atom order.
 __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double inv_scale, double* __restrict__ terms,
                                                    double* __restrict__ forces, double* __restrict__ dudl,
                                                    long long* __restrict__ n_pairs) {
-  __shared__ double red[NACC][kBlk];
+  __shared__ double red[kBlk / 64][NACC];
   __shared__ int last;
   const int K = d.n_reps;
   const int nred = K * kRedChunks;
@@ -911,15 +912,17 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
     double s[NACC] = {0, 0, 0, 0, 0, 0};
     for (int u = c0 + threadIdx.x; u < c1; u += blockDim.x)
       for (int j = 0; j < NACC; ++j) s[j] += d.unit_acc[j * U + u];
-    for (int j = 0; j < NACC; ++j) red[j][threadIdx.x] = s[j];
+    // a butterfly per wave, then the waves in order
+    for (int j = 0; j < NACC; ++j) s[j] = wave_sum(s[j]);
+    if ((threadIdx.x & 63) == 0)
+      for (int j = 0; j < NACC; ++j) red[threadIdx.x >> 6][j] = s[j];
     __syncthreads();
-    for (int off = kBlk / 2; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off)
-        for (int j = 0; j < NACC; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + off];
-      __syncthreads();
-    }
     if (threadIdx.x == 0) {
-      for (int j = 0; j < NACC; ++j) d.chunk_acc[(size_t)blockIdx.x * NACC + j] = red[j][0];
+      for (int j = 0; j < NACC; ++j) {
+        double t = red[0][j];
+        for (int w = 1; w < kBlk / 64; ++w) t += red[w][j];
+        d.chunk_acc[(size_t)blockIdx.x * NACC + j] = t;
+      }
       // publish the chunk sums, then count; the last chunk acquires them all
       last = __hip_atomic_fetch_add(&d.red_done[k], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
              (unsigned int)(kRedChunks - 1);
