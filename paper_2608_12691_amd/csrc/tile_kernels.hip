@@ -66,7 +66,7 @@ struct C4<double> {
 
 template <typename R>
 struct Pot {
-  R rc2, rc, rs, inv_w, alpha, A, B, c2a, sca, inv_h;
+  R rc2, rc, rs, inv_w, alpha, A, B, c2a, sca, inv_h, rs2;
 };
 
 template <typename R>
@@ -82,6 +82,7 @@ __host__ Pot<R> make_pot(const PotConsts& p) {
   o.c2a = (R)p.c2a;
   o.sca = (R)p.sc_alpha;
   o.inv_h = (R)p.inv_h;
+  o.rs2 = p.inv_w > 0 ? (R)(p.rs * p.rs) : (R)p.rc2;
   return o;
 }
 
@@ -616,12 +617,24 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
         if (inm == 0) continue;  // the whole 64-pair tile has moved out of range
         npair += __popcll(inm);
         // only the lanes of in-range pairs execute the pair math
+        // tiles with no in-range pair in the switching shell skip the switch
+        const bool shell = SW && (__ballot(r2 > P.rs2) & inm) != 0;
         if (__builtin_amdgcn_inverse_ballot_w64(inm)) {
-          PairCore<R, SW> pc;
-          pc.template eval<true>(r2, true, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P, dsf);
-          const R u = pc.lj0 * pc.S + pc.el;
-          const R fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
-          const R fs = fr * pc.rinv2;
+          R u, fr, rinv2;
+          if (shell) {
+            PairCore<R, true> pc;
+            pc.template eval<true>(r2, true, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P, dsf);
+            u = pc.lj0 * pc.S + pc.el;
+            fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
+            rinv2 = pc.rinv2;
+          } else {
+            PairCore<R, false> pc;
+            pc.template eval<true>(r2, true, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P, dsf);
+            u = pc.lj0 + pc.el;
+            fr = pc.flj0 + pc.fel;
+            rinv2 = pc.rinv2;
+          }
+          const R fs = fr * rinv2;
           eent += u;
           const R fx = fs * dx, fy = fs * dy, fz = fs * dz;
           fjx += fx;
