@@ -617,8 +617,10 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
         if (inm == 0) continue;  // the whole 64-pair tile has moved out of range
         npair += __popcll(inm);
         // only the lanes of in-range pairs execute the pair math
-        // tiles with no in-range pair in the switching shell skip the switch
-        const bool shell = SW && (__ballot(r2 > P.rs2) & inm) != 0;
+        // FP32 tiles with no in-range pair in the switching shell skip the
+        // switch (in the FP64 kernel the second copy of the pair math costs
+        // more than it saves)
+        const bool shell = SW && (sizeof(R) == 8 || (__ballot(r2 > P.rs2) & inm) != 0);
         if (__builtin_amdgcn_inverse_ballot_w64(inm)) {
           R u, fr, rinv2;
           if (shell) {
