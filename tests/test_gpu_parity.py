@@ -273,3 +273,31 @@ def test_large_pair_forces_fixed_point(precision):
     res, pos = _run(ctx, w, [0.5], positions=[y], flags=2)
     assert res["flags"] == 0
     compare(res, [ref], w, pos, precision, _offsets(w), label="squeezed O-O")
+
+
+@pytest.mark.parametrize("precision", [1, 0], ids=["fp64", "fp32"])
+def test_config1_against_stored_oracle_values(precision):
+    """The HIP path against the stored oracle results (tests/golden), no oracle call at run time."""
+    import json
+    import os
+    from parity import dudl_error, energy_error, force_error
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config1_oracle.json")) as f:
+        g = json.load(f)
+    w = workload(1)
+    atoms = g["force_atoms"]
+    tol = TOL[precision]
+    for name, sched in (("beutler", O.BEUTLER), ("lbf", O.LBF)):
+        ctx = _ctx(w, precision, sched)
+        for c in (c for c in g["cases"] if c["schedule"] == name):
+            print("golden precision=%d schedule=%s lambda=%.2f" % (precision, name, c["lam"]), flush=True)
+            res, _ = _run(ctx, w, [c["lam"]])
+            assert res["flags"] == 0
+            scale = c["abs_terms"]
+            eF = force_error(res["forces"][atoms], np.asarray(c["forces"]))
+            ed = dudl_error(res["dudl"][0], c["terms"][9], scale[9])
+            eE = max(energy_error(res["terms"][0, j], c["terms"][j], scale[j]) for j in range(10))
+            assert eF <= tol["force"], (name, c["lam"], eF)
+            assert ed <= tol["dudl"], (name, c["lam"], ed)
+            assert eE <= tol["energy"], (name, c["lam"], eE)
+            # FP32 distances may put a pair within ~1e-6 A of the cutoff on the other side
+            assert abs(int(res["n_pairs"][0]) - c["n_pairs"]) <= (0 if precision == 1 else 1)
