@@ -301,3 +301,22 @@ def test_config1_against_stored_oracle_values(precision):
             assert eE <= tol["energy"], (name, c["lam"], eE)
             # FP32 distances may put a pair within ~1e-6 A of the cutoff on the other side
             assert abs(int(res["n_pairs"][0]) - c["n_pairs"]) <= (0 if precision == 1 else 1)
+
+
+def test_list_overflow_sets_flag_and_replan_recovers():
+    """A list that outgrows its workspace evaluates nothing and says so; the re-plan gives the oracle's result."""
+    w = workload(1)
+    ctx = _ctx(w, 0, capacity_factor=0.005)
+    pos = ctx.positions(w.systems)
+    lam = ctx.lambdas([0.5])
+    print("overflow: first build with 0.5% of the planned list capacity", flush=True)
+    o = to_numpy(ctx.compute(pos, lam, flags=2))
+    f = ctx.get_flags()
+    assert f & 16, f
+    assert int(o["n_pairs"][0]) == 0 and np.all(o["forces"] == 0.0) and np.all(o["terms"] == 0.0)
+    print("overflow: compute_checked re-plans", flush=True)
+    res = ctx.compute_checked(pos, lam, flags=2)
+    torch.cuda.synchronize()
+    assert res["flags"] == 0
+    ref = oracle_for(w, 0, 0.5, O.BEUTLER)
+    compare(to_numpy(res), [ref], w, [w.systems[0].positions], 0, _offsets(w), label="after re-plan")
