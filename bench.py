@@ -146,6 +146,72 @@ def batched_vs_single(torch, steps, warmup, graph):
     return out
 
 
+def aux_paths(torch, w, traj, lams, W, K):
+    """The rows beside the forward, on the same walk and the FP32 path: the
+    backward for the Cartesian and lambda gradients, the backward with the
+    per-type parameter pass as well, and 4 dihedral CVs with the d-AFED
+    coupling plus the thin lambda/OPES update.  Each mode runs its forward
+    first (the backward needs the state of its own forward); the extra cost
+    of a mode is its time per call minus the forward's."""
+    from paper_2608_12691_amd import alchnb
+    dev = traj.device
+    f64 = torch.float64
+    s = w.systems[0]
+    ctx = alchnb.from_workload(w, precision=alchnb.FP32_FIXED)
+    ctx.compute_checked(traj[0].clone(), lams[0].clone(), flags=alchnb.FORCE_REBUILD)
+    out = ctx.new_outputs()
+    N, T = ctx.N, ctx.n_types
+    g = torch.ones(1, dtype=f64, device=dev)
+    d_pos = torch.empty((N, 3), dtype=f64, device=dev)
+    d_lam = torch.empty(1, dtype=f64, device=dev)
+    d_sig, d_se, d_q = (torch.empty(T, dtype=f64, device=dev) for _ in range(3))
+    sol = np.nonzero(s.is_solute)[0]
+    idx = torch.tensor(sol[:16].reshape(4, 4), dtype=torch.int32, device=dev)
+    minv = torch.ones(N, dtype=f64, device=dev)
+    sv = torch.zeros(4, dtype=f64, device=dev)
+    kap = torch.full((4,), 250.0, dtype=f64, device=dev)
+    kT = 0.0019872042586408316 * 298.0
+    st = ctx.opes_state(capacity=(W + K) // 20 + 8, kT=kT, sigma=0.10, barrier_std=30.0, barrier_expl=5.0)
+    lam_out = torch.zeros(1, dtype=f64, device=dev)
+
+    def fwd(t):
+        ctx.compute(traj[t], lams[t], flags=alchnb.AUTO_REBUILD, out=out)
+
+    def bwd_xl(t):
+        fwd(t)
+        ctx.backward(traj[t], lams[t], g, d_pos=d_pos, d_lambda=d_lam)
+
+    def bwd_all(t):
+        fwd(t)
+        ctx.backward(traj[t], lams[t], g, d_pos=d_pos, d_lambda=d_lam, d_sigma=d_sig, d_sqrt_eps=d_se, d_charge=d_q)
+
+    def cvs_opes(t):
+        fwd(t)
+        ctx.dihedrals(traj[t], idx, mass_inv=minv, s=sv, kappa=kap, forces=out["forces"])
+        ctx.opes_update(st, out["dudl"], lam_out, deposit=(t % 20 == 0))
+
+    ms = {}
+    for name, fn in (("forward", fwd), ("forward+backward_x_lambda", bwd_xl),
+                     ("forward+backward_all", bwd_all), ("forward+cvs+opes", cvs_opes)):
+        for t in range(W):
+            fn(t)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for t in range(W, W + K):
+            fn(t)
+        torch.cuda.synchronize(dev)
+        ms[name] = 1e3 * (time.perf_counter() - t0) / K
+        log("aux", name, "%.4f ms/call" % ms[name])
+    flags = ctx.get_flags()
+    ctx.close()
+    f = ms["forward"]
+    return {"ms_per_call": ms, "calls": K,
+            "backward_x_lambda_us": 1e3 * (ms["forward+backward_x_lambda"] - f),
+            "backward_all_us": 1e3 * (ms["forward+backward_all"] - f),
+            "cvs_opes_us": 1e3 * (ms["forward+cvs+opes"] - f),
+            "device_flags": flags}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +225,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--no-aux", action="store_true")
+    ap.add_argument("--aux-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="after the run, copy a device buffer of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -249,6 +317,8 @@ def main():
     line["device_flags"] = {"fp32": r32["flags"], "fp64": res.get(alchnb.FP64, {}).get("flags")}
     if not args.no_batched:
         line["hrex16"] = batched_vs_single(torch, args.batched_steps, 20, args.mode == "graph")
+    if not args.no_aux:
+        line["aux"] = aux_paths(torch, w, traj, lams, min(W, 20), min(K, args.aux_steps))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, traj_np, lams_np, W, args.cpu_calls)
     if args.copy_calibration > 0:

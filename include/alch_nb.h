@@ -180,7 +180,14 @@ alch_nb_status alch_nb_compute(alch_nb_ctx *ctx, const double *d_pos, const doub
                                const alch_nb_out *out);
 
 /* Gradients of L = sum_k g_k E_total,k for upstream device weights
- * d_grad_energy [K], at the same positions/lambdas as the last compute. */
+ * d_grad_energy [K], at the same positions/lambdas as the last compute:
+ * every gradient comes from that compute's state (forces, dU/dlambda, the
+ * list and the slot coordinates it wrote), so d_pos and d_lambda must be the
+ * inputs of that call.  The parameter gradients are per-atom 64-bit
+ * fixed-point sums (the forces' scale; a value beyond 2^62 units raises
+ * ALCH_NB_FLAG_FIXED_OVERFLOW) added per type in a fixed order, so repeated
+ * calls give identical results.  They need n_types <= 256
+ * (ALCH_NB_E_UNSUPPORTED otherwise). */
 alch_nb_status alch_nb_backward(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda,
                                 const double *d_grad_energy, const alch_nb_grad *grad);
 
@@ -213,7 +220,8 @@ alch_nb_status alch_nb_dihedrals(alch_nb_ctx *ctx, const double *d_pos, int32_t 
  * capacity is reached), then writes lambda (eq. 3) to d_lambda_out [1], the
  * bias and F_theta = -(dlambda/dtheta) dU/dlambda - dU_OPES/dtheta with
  * dU/dlambda read from d_dudl [1] (NULL = 0).  The grid is refreshed on
- * deposition.  Device pointers; FP64; one thread block. */
+ * deposition (a second launch, one block per node).  Device pointers;
+ * FP64; the update itself is one thread block. */
 #define ALCH_NB_OPES_GRID 101
 #define ALCH_NB_OPES_HEADER 16
 int64_t alch_nb_opes_state_size(int32_t capacity);

@@ -183,7 +183,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->red_done = cv.take<unsigned int>(base, K);
   d->lam = cv.take<LamState>(base, K);
   d->last_dudl = cv.take<double>(base, K);
-  d->pgrad_part = cv.take<double>(base, (size_t)kPgBlocks * 3 * ctx->T);
+  d->pg_fix = cv.take<unsigned long long>(base, 3 * SL);
   d->tp32 = cv.take<float4>(base, (size_t)ctx->T * ctx->T);
   d->dsf32 = cv.take<float4>(base, kDsfEntries);
   d->tp64 = cv.take<double4>(base, (size_t)ctx->T * ctx->T);
@@ -732,7 +732,7 @@ alch_nb_status alch_nb_backward(alch_nb_ctx* ctx, const double* d_pos, const dou
     HIPCHK(launch_backward_finish(d, ctx->stream, ctx->p.precision, d_grad_energy, grad->d_pos, grad->d_lambda));
   if (grad->d_sigma || grad->d_sqrt_epsilon || grad->d_charge) {
     if (ctx->T > kMaxTypes) return ALCH_NB_E_UNSUPPORTED;
-    HIPCHK(launch_param_grads(d, ctx->stream, ctx->pc, ctx->p.precision, ctx->p.schedule, d_pos, d_grad_energy,
+    HIPCHK(launch_param_grads(d, ctx->stream, ctx->pc, ctx->p.precision, ctx->p.schedule, d_grad_energy,
                               grad->d_sigma, grad->d_sqrt_epsilon, grad->d_charge));
   }
   return ALCH_NB_OK;

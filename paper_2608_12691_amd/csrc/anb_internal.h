@@ -141,7 +141,7 @@ struct Dev {
   unsigned int* red_done;    // [K] chunks reduced (the last one finishes its box; reset to 0)
   LamState* lam;             // [K]
   double* last_dudl;         // [K] dU/dlambda of the last forward
-  double* pgrad_part;        // [PG_BLOCKS*3*T] parameter-gradient partials
+  unsigned long long* pg_fix;  // [3][SC*64] parameter-gradient sums per slot (fixed point), cleared after each pass
   const float4* tp32;        // [T*T] type-pair sigma, 4 eps, k_e q q, 1/sigma^6 (rounded from FP64)
   const float4* dsf32;       // [kDsfEntries] FP32 DSF pieces (erfc, then the Gaussian term, per interval)
   const double4* tp64;       // [T*T]
@@ -150,6 +150,7 @@ struct Dev {
 enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6 };
 
 constexpr int kPgBlocks = 512;  // blocks of the parameter-gradient pass
+constexpr int kPgLdsTypes = 32;  // the parameter-gradient pass keeps the type-pair table in LDS up to this many types
 constexpr int kMaxTypes = 256;  // atom types supported by the parameter-gradient pass
 
 // lambda/OPES state layout (doubles): header, bias and derivative on the

@@ -46,9 +46,9 @@ hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int pr
                        const TileShape& shape, const double* xin);
 hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int schedule, double* terms,
                            double* forces, double* dudl, long long* n_pairs);
+// pair inputs from the last forward's slot coordinates and list
 hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
-                              const double* xin, const double* g_energy, double* d_sigma, double* d_sqrt_eps,
-                              double* d_charge);
+                              const double* g_energy, double* d_sigma, double* d_sqrt_eps, double* d_charge);
 hipError_t launch_backward_finish(const Dev& d, hipStream_t st, int precision, const double* g_energy,
                                   double* d_pos, double* d_lambda);
 hipError_t launch_dihedrals(hipStream_t st, const double* pos, int n_cv, const int* idx, double* xi, double* dxi,

@@ -1,17 +1,23 @@
 // Backward pass, dihedral collective variables and the lambda/OPES update.
 //
-// - k_pgrad: a second pass over the list that sums, per atom type, the
+// - k_pgrad: a second pass over the list (the work units of the last
+//   forward, its FP64 slot coordinates and image offsets) that sums the
 //   derivatives of the pair energies with respect to sigma, sqrt(epsilon)
-//   and the charge, weighted by the upstream gradient of each box.  Per-block
-//   sums live in LDS (FP64 atomics), block partials are reduced in a fixed
-//   order.  Pair inputs come from the FP64 positions (rounded once).
+//   and the charge, weighted by the upstream gradient of each box, per atom:
+//   in registers over a unit (i-atoms) or an entry (j-atom), then as 64-bit
+//   fixed-point atomics per slot, so the sums do not depend on the order of
+//   the adds.  k_pgrad_final adds the slots of each atom type in a fixed
+//   order (and clears them for the next pass).
 // - k_backward_finish: -g_k F and g_k dU/dlambda from the last forward.
 // - k_dihedrals: dihedral angles, their Cartesian gradients (from the plane
 //   rotation rates and the invariances, see dihedral_grad), the paper's
 //   eq. 16 sum and the d-AFED coupling (eq. 15).
 // - k_opes: mirror-periodic theta (eq. 3), dual OPES bias (eqs. 11-14),
-//   kernel deposition, generalized force on theta.  FP64, one block.
+//   kernel deposition, generalized force on theta.  FP64, one block;
+//   k_opes_grid refreshes the bias on the output grid after a deposition.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "anb_internal.h"
 #include "anb_kernels.h"
@@ -21,12 +27,8 @@ namespace anb {
 
 constexpr int kBlk = 256;
 
-__device__ inline double local_x(const Dev& d, const double* __restrict__ x, int a, int s, int k, double L) {
-  double m = x[3 * a + k] - d.x_build[3 * a + k];
-  m -= L * rint(m / L);
-  return m + (d.xw[3 * a + k] - d.sc_origin[3 * s + k]);
-}
-
+__device__ inline float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp_(double x) { return 1.0 / x; }
 template <typename R>
 __device__ inline R rsq_(R x);
 template <>
@@ -67,7 +69,7 @@ __device__ inline void pair_param_derivs(R r2, bool alch, R sg, R e4, R inv_s6, 
   R ec, ex;
   erfc_exp_((R)pc.alpha * r, ec, ex);
   const R D = (R)kKe * (ec * rinv - (R)pc.A + (R)pc.B * (r - (R)pc.rc));
-  const R isg = R(1) / sg;
+  const R isg = rcp_(sg);
   if (!alch) {
     dsig = S * flj * isg;
     deps = S * lj4;
@@ -96,20 +98,69 @@ __device__ inline void pair_param_derivs(R r2, bool alch, R sg, R e4, R inv_s6, 
   }
 }
 
+__device__ inline void pg_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// sum over the lanes that differ only in the bits of m (butterfly, the
+// same tree in every lane)
+__device__ inline double lane_sum(double v, int m0, int m1, int m2) {
+  v += __shfl_xor(v, m0);
+  v += __shfl_xor(v, m1);
+  v += __shfl_xor(v, m2);
+  return v;
+}
+
+// v * scale rounded into a 64-bit fixed-point slot sum
+__device__ inline void add_fixed(unsigned long long* p, double v, double scale, unsigned int* flags) {
+  const double x = v * scale;
+  if (!(fabs(x) < 0x1p62)) {
+    atomicOr(flags, 1u);
+    return;
+  }
+  const long long iv = __double2ll_rn(x);
+  if (iv != 0) atomicAdd(p, (unsigned long long)iv);
+}
+
+// One wave per work unit (grid-stride over the units): lane (jl, il) as in
+// the tile kernel.  i-atom sums stay in registers for the whole unit (one
+// super-cluster), j-atom sums for one entry.
 template <typename R, int SCHED, bool SW>
-__global__ void __launch_bounds__(kBlk) k_pgrad(Dev d, PotConsts pc, const double* __restrict__ xin,
-                                                const double* __restrict__ g_energy) {
-  __shared__ double acc[3 * kMaxTypes];
+__global__ void __launch_bounds__(kBlk) k_pgrad(Dev d, PotConsts pc, const double* __restrict__ g_energy,
+                                                double scale) {
+  using TP = typename std::conditional<sizeof(R) == 4, float4, double4>::type;
   __shared__ double se_t[kMaxTypes], q_t[kMaxTypes];
+  // the type-pair table (rounded to the pair precision) in LDS when it fits
+  // (T <= 32), else read from HBM
+  __shared__ TP tp_s[kPgLdsTypes * kPgLdsTypes];
+  // the current super-cluster's slots and the current unit's j-clusters
+  // (image offset added; lane (k, t): atom t of entry k), one copy per wave
+  __shared__ double4 ip_all[kBlk], jp_all[kBlk];
+  __shared__ int it_all[kBlk], jt_all[kBlk], js_all[kBlk];
   const int T = d.n_types;
-  for (int i = threadIdx.x; i < 3 * T; i += blockDim.x) acc[i] = 0.0;
+  const bool tp_lds = T <= kPgLdsTypes;
+  const TP* __restrict__ tpg = reinterpret_cast<const TP*>(sizeof(R) == 4 ? (const void*)d.tp32 : (const void*)d.tp64);
   for (int i = threadIdx.x; i < T; i += blockDim.x) {
     se_t[i] = sqrt(d.type_eps[i]);
     q_t[i] = d.type_q[i];
   }
+  if (tp_lds)
+    for (int i = threadIdx.x; i < T * T; i += blockDim.x) tp_s[i] = tpg[i];
   __syncthreads();
+  const TP* __restrict__ tpt = tp_lds ? tp_s : tpg;
+  double4* ip_s = ip_all + (threadIdx.x & ~63);
+  int* it_s = it_all + (threadIdx.x & ~63);
+  double4* jp_s = jp_all + (threadIdx.x & ~63);
+  int* jt_s = jt_all + (threadIdx.x & ~63);
+  int* js_s = js_all + (threadIdx.x & ~63);
   const int lane = threadIdx.x & 63;
   const int il = lane & 7, jl = lane >> 3;
+  const int slots = d.sc_cap * kSc;
+  unsigned long long* acc0 = d.pg_fix;
+  unsigned long long* acc1 = d.pg_fix + slots;
+  unsigned long long* acc2 = d.pg_fix + 2 * (size_t)slots;
   const int n_units = d.ctr[CTR_NUNIT];
   const int wave = blockIdx.x * (kBlk / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int n_waves = gridDim.x * (kBlk / 64);
@@ -118,71 +169,147 @@ __global__ void __launch_bounds__(kBlk) k_pgrad(Dev d, PotConsts pc, const doubl
     const int s = U.x, rep = U.w;
     const double g = g_energy[rep];
     if (g == 0.0) continue;
-    const ReplicaInfo& rp = d.reps[rep];
-    const double L0 = rp.box[0], L1 = rp.box[1], L2 = rp.box[2];
     const LamState lam = d.lam[rep];
     const R la0 = (R)lam.a[0], la1 = (R)lam.a[1];
+    {
+      static_assert(kMaxEpu * kCl == 64, "one lane per atom of a unit's entries");
+      const int k = lane >> 3, t = lane & 7, e = U.y + k;
+      double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+      int ty = 0, jsl = 0;
+      const double4 pi = d.pos64[s * kSc + lane];
+      const int ti = d.slot_type[s * kSc + lane];
+      if (e < U.z) {
+        jsl = d.ent_jc[e] * kCl + t;
+        const double4 off = d.ent_off[e];
+        const double4 p = d.pos64[jsl];
+        v = make_double4(p.x + off.x, p.y + off.y, p.z + off.z, 0.0);
+        ty = d.slot_type[jsl];
+      }
+      pg_wave_sync();
+      ip_s[lane] = pi;
+      it_s[lane] = ti;
+      jp_s[lane] = v;
+      jt_s[lane] = ty;
+      js_s[lane] = jsl;
+      pg_wave_sync();
+    }
+    // sums in the pair precision over one unit (i) or entry (j), then FP64
+    R ai0[kScCl], ai1[kScCl], ai2[kScCl];
+#pragma unroll
+    for (int c = 0; c < kScCl; ++c) ai0[c] = ai1[c] = ai2[c] = R(0);
+    // entry words and pair masks are read one entry ahead (scalar loads)
+    uint32_t info_n = d.ent_info[U.y];
+    unsigned long long m_n[kScCl];
+#pragma unroll
+    for (int c = 0; c < kScCl; ++c) m_n[c] = d.ent_mask[(size_t)U.y * kScCl + c];
     for (int e = U.y; e < U.z; ++e) {
-      const int jc = d.ent_jc[e];
-      const uint32_t info = d.ent_info[e];
+      const uint32_t info = info_n;
+      unsigned long long m[kScCl];
+#pragma unroll
+      for (int c = 0; c < kScCl; ++c) m[c] = m_n[c];
+      if (e + 1 < U.z) {
+        info_n = d.ent_info[e + 1];
+#pragma unroll
+        for (int c = 0; c < kScCl; ++c) m_n[c] = d.ent_mask[(size_t)(e + 1) * kScCl + c];
+      }
       const uint32_t imask = info & 0xffu;
       const bool alch = ((info >> 8) & 3u) == KIND_ALCH;
-      const int code = (int)((info >> 16) & 31u);
-      const int sj = jc >> 3;
-      const double odx = d.sc_origin[3 * sj] + (double)(code % 3 - 1) * L0 - d.sc_origin[3 * s];
-      const double ody = d.sc_origin[3 * sj + 1] + (double)((code / 3) % 3 - 1) * L1 - d.sc_origin[3 * s + 1];
-      const double odz = d.sc_origin[3 * sj + 2] + (double)(code / 9 - 1) * L2 - d.sc_origin[3 * s + 2];
-      const int aj = max(0, d.slot_atom[jc * kCl + jl]);
-      const double xj = local_x(d, xin, aj, sj, 0, L0) + odx;
-      const double yj = local_x(d, xin, aj, sj, 1, L1) + ody;
-      const double zj = local_x(d, xin, aj, sj, 2, L2) + odz;
-      const int tj = d.atom_type[aj];
+      const int kj = (e - U.y) * kCl + jl;
+      const int jsl = js_s[kj];
+      const double4 pj = jp_s[kj];
+      const double xj = pj.x, yj = pj.y, zj = pj.z;
+      const int tj = jt_s[kj];
+      const R sej = (R)se_t[tj], qj = (R)q_t[tj];
+      R bj0 = R(0), bj1 = R(0), bj2 = R(0);
+#pragma unroll
       for (int c = 0; c < kScCl; ++c) {
         if (!(imask & (1u << c))) continue;
-        const bool valid = (d.ent_mask[(size_t)e * kScCl + c] >> lane) & 1ull;
-        const int ai = max(0, d.slot_atom[s * kSc + c * kCl + il]);
-        const R dx = (R)(xj - local_x(d, xin, ai, s, 0, L0));
-        const R dy = (R)(yj - local_x(d, xin, ai, s, 1, L1));
-        const R dz = (R)(zj - local_x(d, xin, ai, s, 2, L2));
+        const double4 pi = ip_s[c * kCl + il];
+        const R dx = (R)(xj - pi.x), dy = (R)(yj - pi.y), dz = (R)(zj - pi.z);
         const R r2 = dx * dx + dy * dy + dz * dz;
-        if (!valid || !(r2 < (R)pc.rc2)) continue;
-        const int ti = d.atom_type[ai];
-        const double4 tp = d.tp64[ti * T + tj];
+        const bool valid = ((m[c] >> lane) & 1ull) && r2 < (R)pc.rc2;
+        if (__ballot(valid) == 0) continue;
+        const int ti = it_s[c * kCl + il];
+        const TP tp = tpt[ti * T + tj];
         R dsig, deps, dqq;
-        pair_param_derivs<R, SCHED, SW>(r2, alch, (R)tp.x, (R)tp.y, (R)tp.w, la0, la1, pc, dsig, deps, dqq);
-        const double ws = g * 0.5 * (double)dsig, we = g * (double)deps, wq = g * (double)dqq;
-        atomicAdd(&acc[ti], ws);
-        atomicAdd(&acc[tj], ws);
-        atomicAdd(&acc[T + ti], we * se_t[tj]);
-        atomicAdd(&acc[T + tj], we * se_t[ti]);
-        atomicAdd(&acc[2 * T + ti], wq * q_t[tj]);
-        atomicAdd(&acc[2 * T + tj], wq * q_t[ti]);
+        pair_param_derivs<R, SCHED, SW>(valid ? r2 : R(1), alch, (R)tp.x, (R)tp.y, (R)tp.w, la0, la1, pc, dsig,
+                                        deps, dqq);
+        const R ws = valid ? R(0.5) * dsig : R(0);
+        const R we = valid ? deps : R(0);
+        const R wq = valid ? dqq : R(0);
+        ai0[c] += ws;
+        ai1[c] += we * sej;
+        ai2[c] += wq * qj;
+        bj0 += ws;
+        bj1 += we * (R)se_t[ti];
+        bj2 += wq * (R)q_t[ti];
+      }
+      // the j-atom's sums over il, weighted by the box's upstream gradient
+      const double vj0 = lane_sum(g * (double)bj0, 1, 2, 4);
+      const double vj1 = lane_sum(g * (double)bj1, 1, 2, 4);
+      const double vj2 = lane_sum(g * (double)bj2, 1, 2, 4);
+      if (il == 0) {
+        add_fixed(acc0 + jsl, vj0, scale, d.flags);
+        add_fixed(acc1 + jsl, vj1, scale, d.flags);
+        add_fixed(acc2 + jsl, vj2, scale, d.flags);
+      }
+    }
+    // the i-atoms' sums over jl
+#pragma unroll
+    for (int c = 0; c < kScCl; ++c) {
+      const double v0 = lane_sum(g * (double)ai0[c], 8, 16, 32);
+      const double v1 = lane_sum(g * (double)ai1[c], 8, 16, 32);
+      const double v2 = lane_sum(g * (double)ai2[c], 8, 16, 32);
+      if (jl == 0) {
+        const int isl = s * kSc + c * kCl + il;
+        add_fixed(acc0 + isl, v0, scale, d.flags);
+        add_fixed(acc1 + isl, v1, scale, d.flags);
+        add_fixed(acc2 + isl, v2, scale, d.flags);
       }
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < 3 * T; i += blockDim.x) d.pgrad_part[(size_t)blockIdx.x * 3 * T + i] = acc[i];
 }
 
-// Fixed-order sum of the block partials.
-__global__ void k_pgrad_final(Dev d, int n_blocks, double* __restrict__ d_sigma, double* __restrict__ d_sqrt_eps,
-                              double* __restrict__ d_charge) {
+// Block (component, type): the slot sums of that type's atoms, each thread
+// over a fixed stride of slots, then the waves' butterflies and the waves in
+// order; the slots it read are cleared for the next pass.
+constexpr int kPgFinalBlk = 1024;
+__global__ void __launch_bounds__(kPgFinalBlk) k_pgrad_final(Dev d, double inv_scale, double* __restrict__ d_sigma,
+                                                             double* __restrict__ d_sqrt_eps,
+                                                             double* __restrict__ d_charge) {
+  __shared__ double part[kPgFinalBlk / 64];
   const int T = d.n_types;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 3 * T; i += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int b = 0; b < n_blocks; ++b) s += d.pgrad_part[(size_t)b * 3 * T + i];
-    const int which = i / T, t = i % T;
-    double* out = which == 0 ? d_sigma : (which == 1 ? d_sqrt_eps : d_charge);
-    if (out) out[t] = s;
+  const int comp = blockIdx.x / T, t = blockIdx.x % T;
+  const int slots = d.sc_cap * kSc;
+  unsigned long long* acc = d.pg_fix + (size_t)comp * slots;
+  double sum = 0.0;
+#pragma unroll 4
+  for (int sl = threadIdx.x; sl < slots; sl += kPgFinalBlk) {
+    if (d.slot_type[sl] != t) continue;  // padding slots carry type 0 and zero sums
+    const long long v = (long long)acc[sl];
+    if (v != 0) {
+      sum += (double)v * inv_scale;
+      acc[sl] = 0ull;
+    }
+  }
+  sum = lane_sum(sum, 1, 2, 4);
+  sum = lane_sum(sum, 8, 16, 32);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double total = 0.0;
+    for (int w = 0; w < kPgFinalBlk / 64; ++w) total += part[w];
+    double* out = comp == 0 ? d_sigma : (comp == 1 ? d_sqrt_eps : d_charge);
+    if (out) out[t] = total;
   }
 }
 
 hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
-                              const double* xin, const double* g_energy, double* d_sigma, double* d_sqrt_eps,
-                              double* d_charge) {
+                              const double* g_energy, double* d_sigma, double* d_sqrt_eps, double* d_charge) {
   const dim3 G(kPgBlocks), B(kBlk);
   const bool sw = pc.inv_w > 0;
-#define PG(R, S, W) hipLaunchKernelGGL((k_pgrad<R, S, W>), G, B, 0, st, d, pc, xin, g_energy)
+  const double scale = fixed_scale(precision);
+#define PG(R, S, W) hipLaunchKernelGGL((k_pgrad<R, S, W>), G, B, 0, st, d, pc, g_energy, scale)
   if (precision == 0) {
     if (schedule == 0) { if (sw) PG(float, 0, true); else PG(float, 0, false); }
     else { if (sw) PG(float, 1, true); else PG(float, 1, false); }
@@ -191,7 +318,8 @@ hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc,
     else { if (sw) PG(double, 1, true); else PG(double, 1, false); }
   }
 #undef PG
-  hipLaunchKernelGGL(k_pgrad_final, dim3(1), dim3(kBlk), 0, st, d, (int)kPgBlocks, d_sigma, d_sqrt_eps, d_charge);
+  hipLaunchKernelGGL(k_pgrad_final, dim3(3 * d.n_types), dim3(kPgFinalBlk), 0, st, d, 1.0 / scale, d_sigma, d_sqrt_eps,
+                     d_charge);
   return hipGetLastError();
 }
 
@@ -357,7 +485,7 @@ __device__ inline void pgauss(double dth, double sig, double& v, double& dv) {
 // Block-wide sums over the kernel centres at theta: weighted (Standard) and
 // unweighted (Explore) density and their theta derivatives.  Fixed order.
 __device__ void kde_sums(const double* cen, const double* w, int n, double th, double sig, double out[4]) {
-  __shared__ double red[4][kBlk];
+  __shared__ double red[4][kBlk / 64];
   double a[4] = {0, 0, 0, 0};
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     double v, dv;
@@ -367,14 +495,20 @@ __device__ void kde_sums(const double* cen, const double* w, int n, double th, d
     a[2] += v;
     a[3] += dv;
   }
-  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = a[k];
-  __syncthreads();
-  for (int off = kBlk / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off)
-      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
-    __syncthreads();
+  // butterflies within each wave, then the waves in order (the same order
+  // in every thread)
+  for (int k = 0; k < 4; ++k) {
+    a[k] = lane_sum(a[k], 1, 2, 4);
+    a[k] = lane_sum(a[k], 8, 16, 32);
   }
-  for (int k = 0; k < 4; ++k) out[k] = red[k][0];
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x >> 6] = a[k];
+  __syncthreads();
+  for (int k = 0; k < 4; ++k) {
+    double t = red[k][0];
+    for (int q = 1; q < kBlk / 64; ++q) t += red[k][q];
+    out[k] = t;
+  }
   __syncthreads();
 }
 
@@ -444,18 +578,25 @@ __global__ void __launch_bounds__(kBlk) k_opes(double* __restrict__ st, const do
     h[OPES_FTHETA] = -dl * (dudl ? dudl[0] : 0.0) - dU;
     if (lam_out) lam_out[0] = lam;
   }
-  if (deposit) {
-    // bias on the output grid (diagnostics), one node at a time
-    for (int g = 0; g < OPES_GRID_N; ++g) {
-      const double tg = 2.0 * g / OPES_GRID_N;
-      kde_sums(cen, w, n, tg, sig, sums);
-      double Ug, dUg;
-      opes_bias(h, sums, Ug, dUg);
-      if (threadIdx.x == 0) {
-        grid_u[g] = Ug;
-        grid_du[g] = dUg;
-      }
-    }
+}
+
+// The bias on the output grid (diagnostics) after a deposition: block g
+// takes node g.
+__global__ void __launch_bounds__(kBlk) k_opes_grid(double* __restrict__ st) {
+  const double* h = st;
+  const int cap = (int)h[OPES_CAP];
+  double* grid_u = st + OPES_HEADER;
+  double* grid_du = grid_u + OPES_GRID_N;
+  const double* cen = grid_du + OPES_GRID_N;
+  const double* w = cen + cap;
+  const int g = blockIdx.x;
+  double sums[4];
+  kde_sums(cen, w, (int)h[OPES_N], 2.0 * g / OPES_GRID_N, h[OPES_SIGMA], sums);
+  double Ug, dUg;
+  opes_bias(h, sums, Ug, dUg);
+  if (threadIdx.x == 0) {
+    grid_u[g] = Ug;
+    grid_du[g] = dUg;
   }
 }
 
@@ -482,6 +623,7 @@ hipError_t launch_opes_init(hipStream_t st, double* state, int cap, double kT, d
 
 hipError_t launch_opes(hipStream_t st, double* state, const double* dudl, double* lambda_out, int deposit) {
   hipLaunchKernelGGL(k_opes, dim3(1), dim3(kBlk), 0, st, state, dudl, lambda_out, deposit);
+  if (deposit) hipLaunchKernelGGL(k_opes_grid, dim3(OPES_GRID_N), dim3(kBlk), 0, st, state);
   return hipGetLastError();
 }
 
