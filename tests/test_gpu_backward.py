@@ -198,3 +198,27 @@ def test_opes_update_against_oracle():
     gth, gu, gdu = ref.grid()
     assert np.allclose(st[16:16 + 101].cpu().numpy(), gu, rtol=1e-10, atol=1e-10)
     assert np.allclose(st[16 + 101:16 + 202].cpu().numpy(), gdu, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+def test_backward_param_grads_repeat_bitwise(precision):
+    """The per-type gradients are fixed-point slot sums added in a fixed order: repeats are identical."""
+    w = workload(2)
+    ctx = _ctx(w, precision)
+    pos = ctx.positions(w.systems)
+    lam = ctx.lambdas([0.55])
+    g = torch.ones(1, dtype=torch.float64, device=ctx.device)
+    T = ctx.n_types
+    outs = []
+    for rep in range(3):
+        print("backward repeat %d precision %d" % (rep, precision), flush=True)
+        ctx.compute(pos, lam, flags=2 if rep == 0 else 0)
+        dsig, dse, dq = (torch.zeros(T, dtype=torch.float64, device=ctx.device) for _ in range(3))
+        ctx.backward(pos, lam, g, d_sigma=dsig, d_sqrt_eps=dse, d_charge=dq)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in (dsig, dse, dq)])
+    assert ctx.get_flags() == 0
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+    assert np.any(outs[0][0] != 0.0) and np.any(outs[0][2] != 0.0)
