@@ -149,8 +149,6 @@ struct Dev {
 
 enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6 };
 
-constexpr int kPgBlocks = 512;  // blocks of the parameter-gradient pass
-constexpr int kPgLdsTypes = 32;  // the parameter-gradient pass keeps the type-pair table in LDS up to this many types
 constexpr int kMaxTypes = 256;  // atom types supported by the parameter-gradient pass
 
 // lambda/OPES state layout (doubles): header, bias and derivative on the

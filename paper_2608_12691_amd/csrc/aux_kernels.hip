@@ -26,6 +26,8 @@
 namespace anb {
 
 constexpr int kBlk = 256;
+constexpr int kPgBlocks = 1024;   // blocks of the parameter-gradient pass (4 waves per SIMD)
+constexpr int kPgLdsTypes = 32;   // the type-pair table goes to LDS up to this many types
 
 __device__ inline float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double rcp_(double x) { return 1.0 / x; }
@@ -106,7 +108,8 @@ __device__ inline void pg_wave_sync() {
 
 // sum over the lanes that differ only in the bits of m (butterfly, the
 // same tree in every lane)
-__device__ inline double lane_sum(double v, int m0, int m1, int m2) {
+template <typename V>
+__device__ inline V lane_sum(V v, int m0, int m1, int m2) {
   v += __shfl_xor(v, m0);
   v += __shfl_xor(v, m1);
   v += __shfl_xor(v, m2);
@@ -245,9 +248,9 @@ __global__ void __launch_bounds__(kBlk) k_pgrad(Dev d, PotConsts pc, const doubl
         bj2 += wq * (R)q_t[ti];
       }
       // the j-atom's sums over il, weighted by the box's upstream gradient
-      const double vj0 = lane_sum(g * (double)bj0, 1, 2, 4);
-      const double vj1 = lane_sum(g * (double)bj1, 1, 2, 4);
-      const double vj2 = lane_sum(g * (double)bj2, 1, 2, 4);
+      const double vj0 = g * (double)lane_sum(bj0, 1, 2, 4);
+      const double vj1 = g * (double)lane_sum(bj1, 1, 2, 4);
+      const double vj2 = g * (double)lane_sum(bj2, 1, 2, 4);
       if (il == 0) {
         add_fixed(acc0 + jsl, vj0, scale, d.flags);
         add_fixed(acc1 + jsl, vj1, scale, d.flags);
@@ -257,9 +260,9 @@ __global__ void __launch_bounds__(kBlk) k_pgrad(Dev d, PotConsts pc, const doubl
     // the i-atoms' sums over jl
 #pragma unroll
     for (int c = 0; c < kScCl; ++c) {
-      const double v0 = lane_sum(g * (double)ai0[c], 8, 16, 32);
-      const double v1 = lane_sum(g * (double)ai1[c], 8, 16, 32);
-      const double v2 = lane_sum(g * (double)ai2[c], 8, 16, 32);
+      const double v0 = g * (double)lane_sum(ai0[c], 8, 16, 32);
+      const double v1 = g * (double)lane_sum(ai1[c], 8, 16, 32);
+      const double v2 = g * (double)lane_sum(ai2[c], 8, 16, 32);
       if (jl == 0) {
         const int isl = s * kSc + c * kCl + il;
         add_fixed(acc0 + isl, v0, scale, d.flags);
