@@ -107,7 +107,7 @@ struct Dev {
   int* cl_n;                 // [SC*8]
   int* slot_atom;            // [SC*64] atom index or -1
   int* atom_slot;            // [N]
-  double4* atom_off;         // [N] build-time offset of the atom from its SC origin (set with the slots)
+  double4* atom_off;         // [N] build-time offset of the atom from its SC origin, .w = slot + 1 (set with the slots)
   double4* atom_box;         // [N] box of the atom's replica (set with the slots)
   double4* slot_xw;          // [SC*64] build-time wrapped position of the slot's atom
   int* slot_comp;            // [SC*64] exclusion component of the slot's atom (-1 = padding)

@@ -145,12 +145,12 @@ __global__ void __launch_bounds__(kBlk) k_pgrad(Dev d, PotConsts pc, const doubl
   const int T = d.n_types;
   const bool tp_lds = T <= kPgLdsTypes;
   const TP* __restrict__ tpg = reinterpret_cast<const TP*>(sizeof(R) == 4 ? (const void*)d.tp32 : (const void*)d.tp64);
-  for (int i = threadIdx.x; i < T; i += blockDim.x) {
+  for (int i = threadIdx.x; i < T; i += kBlk) {
     se_t[i] = sqrt(d.type_eps[i]);
     q_t[i] = d.type_q[i];
   }
   if (tp_lds)
-    for (int i = threadIdx.x; i < T * T; i += blockDim.x) tp_s[i] = tpg[i];
+    for (int i = threadIdx.x; i < T * T; i += kBlk) tp_s[i] = tpg[i];
   __syncthreads();
   const TP* __restrict__ tpt = tp_lds ? tp_s : tpg;
   double4* ip_s = ip_all + (threadIdx.x & ~63);
@@ -329,11 +329,11 @@ hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc,
 // d_pos += g_k dU/dx = -g_k F ; d_lambda = g_k dU/dlambda (last forward).
 __global__ void k_backward_finish(Dev d, double inv_scale, const double* __restrict__ g_energy, double* d_pos,
                                   double* d_lambda) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.x * kBlk + threadIdx.x;
   if (d_lambda && t < d.n_reps) d_lambda[t] = g_energy[t] * d.last_dudl[t];
   if (!d_pos) return;
   const int slots = d.sc_cap * kSc;
-  for (int a = t; a < d.n_atoms; a += gridDim.x * blockDim.x) {
+  for (int a = t; a < d.n_atoms; a += gridDim.x * kBlk) {
     const double g = g_energy[d.grids[d.atom_grid[a]].replica];
     const int sl = d.atom_slot[a];
     for (int c = 0; c < 3; ++c) d_pos[3 * a + c] -= g * (double)(long long)d.ffix[c * slots + sl] * inv_scale;
@@ -490,7 +490,7 @@ __device__ inline void pgauss(double dth, double sig, double& v, double& dv) {
 __device__ void kde_sums(const double* cen, const double* w, int n, double th, double sig, double out[4]) {
   __shared__ double red[4][kBlk / 64];
   double a[4] = {0, 0, 0, 0};
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+  for (int j = threadIdx.x; j < n; j += kBlk) {
     double v, dv;
     pgauss(th - cen[j], sig, v, dv);
     a[0] += w[j] * v;
@@ -606,7 +606,7 @@ __global__ void __launch_bounds__(kBlk) k_opes_grid(double* __restrict__ st) {
 __global__ void k_opes_init(double* st, int cap, double kT, double sigma, double de_std, double de_expl,
                             double theta0) {
   const int total = OPES_HEADER + 2 * OPES_GRID_N + 2 * cap;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) st[i] = 0.0;
+  for (int i = blockIdx.x * kBlk + threadIdx.x; i < total; i += gridDim.x * kBlk) st[i] = 0.0;
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st[OPES_THETA] = theta0;

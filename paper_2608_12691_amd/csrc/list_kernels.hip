@@ -354,8 +354,9 @@ __device__ void ph_build_sc(const Dev& d) {
     double q[3] = {0.0, 0.0, 0.0};
     if (v) {
       for (int k = 0; k < 3; ++k) q[k] = w[k] - org[k];
-      // what the per-call pass adds to the displacement since the build
-      d.atom_off[a] = make_double4(q[0], q[1], q[2], 0.0);
+      // what the per-call pass adds to the displacement since the build,
+      // and the slot + 1 (0 = never placed)
+      d.atom_off[a] = make_double4(q[0], q[1], q[2], (double)(sl + 1));
       d.atom_box[a] = d.sc_box[s];
     }
     d.pos32[sl] = make_float4((float)q[0], (float)q[1], (float)q[2], d.q32[sl]);

@@ -25,8 +25,10 @@ namespace anb {
 
 constexpr int kBlk = 256;
 
-__device__ inline int gtid() { return blockIdx.x * blockDim.x + threadIdx.x; }
-__device__ inline int gthreads() { return gridDim.x * blockDim.x; }
+// every kernel here runs kBlk-thread blocks (k_init: one block, thread 0
+// only); the constant spares the load of the block size at kernel start
+__device__ inline int gtid() { return blockIdx.x * kBlk + threadIdx.x; }
+__device__ inline int gthreads() { return gridDim.x * kBlk; }
 
 // ------------------------------------------------------------ math by type
 
@@ -854,24 +856,29 @@ __global__ void __launch_bounds__(kBlk) k_prepare(Dev d, const double* __restric
     d.barrier[0] = 0u;
     for (int g = 1; g <= kBarGroups; ++g) d.barrier[kBarStride * g] = 0u;
   }
-  const bool have_list = d.ctr[CTR_NBUILD] > 0;
   bool moved = false, bad = false;
   for (int a = t; a < d.n_atoms; a += gthreads()) {
+    // per-atom records written with the slots (zero before the first
+    // build; off.w = slot + 1): every load here is independent of the
+    // others, and each is needed on every path, so they all go out together
     const double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z))) bad = true;  // reported; the values still flow
-    if (!have_list || mode == 2) continue;  // the list build writes the slot data
-    // per-atom records written with the slots: every load here is
-    // independent of the others
     const double4 L = d.atom_box[a], off = d.atom_off[a];
-    const int sl = d.atom_slot[a];
+    const double xb = d.x_build[3 * a], yb = d.x_build[3 * a + 1], zb = d.x_build[3 * a + 2];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) bad = true;  // reported; the values still flow
     const double Lk[3] = {L.x, L.y, L.z}, ok[3] = {off.x, off.y, off.z};
-    double dd[3] = {x - d.x_build[3 * a], y - d.x_build[3 * a + 1], z - d.x_build[3 * a + 2]};
+    double dd[3] = {x - xb, y - yb, z - zb};
     double r2 = 0;
     for (int k = 0; k < 3; ++k) {
       dd[k] -= Lk[k] * rint(dd[k] / Lk[k]);
       r2 += dd[k] * dd[k];
     }
+    // (an atom not yet placed has a zero box: NaN distance, never moved)
     if (r2 > half_skin2) moved = true;
+    // (the test reads every component of off, so that its load is not
+    // split and the rest of it held back behind the branch)
+    const bool placed = off.w > 0.0 && !isnan(off.x + off.y + off.z);
+    if (!placed || mode == 2) continue;  // the list build writes the slot data
+    const int sl = (int)off.w - 1;
     // Coordinates relative to the atom's SC origin in the image it had at
     // the build (displacement since the build plus the build-time offset),
     // and cleared force accumulators; the charges in .w stay from the
@@ -891,7 +898,7 @@ __global__ void __launch_bounds__(kBlk) k_prepare(Dev d, const double* __restric
     d.ffix[2 * slots + sl] = 0ull;
   }
   if (bad) atomicOr(d.flags, 4u);
-  if (moved) {
+  if (moved && mode != 2) {
     if (mode == 1) __atomic_store_n(d.rebuild, 1, __ATOMIC_RELAXED);
     else atomicOr(d.flags, 2u);
   }
@@ -925,7 +932,7 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
     const int c1 = u0 + (int)((long long)(u1 - u0) * (c + 1) / kRedChunks);
     const size_t U = (size_t)d.unit_cap;
     double s[NACC] = {0, 0, 0, 0, 0, 0};
-    for (int u = c0 + threadIdx.x; u < c1; u += blockDim.x)
+    for (int u = c0 + threadIdx.x; u < c1; u += kBlk)
       for (int j = 0; j < NACC; ++j) s[j] += d.unit_acc[j * U + u];
     // a butterfly per wave, then the waves in order
     for (int j = 0; j < NACC; ++j) s[j] = wave_sum(s[j]);
@@ -973,7 +980,7 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
   if (!forces) return;
   // one slot per thread: its three sums and its atom index are independent loads
   const int slots = d.sc_cap * kSc;
-  for (int sl = (blockIdx.x - nred) * blockDim.x + threadIdx.x; sl < slots; sl += (gridDim.x - nred) * blockDim.x) {
+  for (int sl = (blockIdx.x - nred) * kBlk + threadIdx.x; sl < slots; sl += (gridDim.x - nred) * kBlk) {
     const int a = d.slot_atom[sl];
     const long long fx = (long long)d.ffix[sl];
     const long long fy = (long long)d.ffix[slots + sl];
