@@ -277,6 +277,7 @@ __global__ void __launch_bounds__(kBlk) k_pgrad(Dev d, PotConsts pc, const doubl
 // over a fixed stride of slots, then the waves' butterflies and the waves in
 // order; the slots it read are cleared for the next pass.
 constexpr int kPgFinalBlk = 1024;
+constexpr int kPgFinalRun = 16;
 __global__ void __launch_bounds__(kPgFinalBlk) k_pgrad_final(Dev d, double inv_scale, double* __restrict__ d_sigma,
                                                              double* __restrict__ d_sqrt_eps,
                                                              double* __restrict__ d_charge) {
@@ -286,13 +287,22 @@ __global__ void __launch_bounds__(kPgFinalBlk) k_pgrad_final(Dev d, double inv_s
   const int slots = d.sc_cap * kSc;
   unsigned long long* acc = d.pg_fix + (size_t)comp * slots;
   double sum = 0.0;
-#pragma unroll 4
-  for (int sl = threadIdx.x; sl < slots; sl += kPgFinalBlk) {
-    if (d.slot_type[sl] != t) continue;  // padding slots carry type 0 and zero sums
-    const long long v = (long long)acc[sl];
-    if (v != 0) {
-      sum += (double)v * inv_scale;
-      acc[sl] = 0ull;
+  // kPgFinalRun slots per thread per round, all loads of a round issued
+  // together (padding slots carry type 0 and zero sums)
+  for (int base = 0; base < slots; base += kPgFinalBlk * kPgFinalRun) {
+    int ty[kPgFinalRun];
+    long long v[kPgFinalRun];
+#pragma unroll
+    for (int i = 0; i < kPgFinalRun; ++i) {
+      const int sl = base + i * kPgFinalBlk + threadIdx.x;
+      ty[i] = sl < slots ? d.slot_type[sl] : -1;
+      v[i] = sl < slots ? (long long)acc[sl] : 0ll;
+    }
+#pragma unroll
+    for (int i = 0; i < kPgFinalRun; ++i) {
+      if (ty[i] != t || v[i] == 0) continue;
+      sum += (double)v[i] * inv_scale;
+      acc[base + i * kPgFinalBlk + threadIdx.x] = 0ull;
     }
   }
   sum = lane_sum(sum, 1, 2, 4);
