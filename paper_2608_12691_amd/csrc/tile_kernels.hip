@@ -932,8 +932,18 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
     const int c1 = u0 + (int)((long long)(u1 - u0) * (c + 1) / kRedChunks);
     const size_t U = (size_t)d.unit_cap;
     double s[NACC] = {0, 0, 0, 0, 0, 0};
-    for (int u = c0 + threadIdx.x; u < c1; u += kBlk)
-      for (int j = 0; j < NACC; ++j) s[j] += d.unit_acc[j * U + u];
+    // four units per thread per round, their loads issued together
+    for (int u = c0 + threadIdx.x; u < c1; u += 4 * kBlk) {
+      double v[4][NACC];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < NACC; ++j) v[q][j] = u + q * kBlk < c1 ? d.unit_acc[j * U + u + q * kBlk] : 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int j = 0; j < NACC; ++j) s[j] += v[q][j];
+    }
     // a butterfly per wave, then the waves in order
     for (int j = 0; j < NACC; ++j) s[j] = wave_sum(s[j]);
     if ((threadIdx.x & 63) == 0)
@@ -985,6 +995,9 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
     const long long fx = (long long)d.ffix[sl];
     const long long fy = (long long)d.ffix[slots + sl];
     const long long fz = (long long)d.ffix[2 * slots + sl];
+    // an empty statement that reads the sums: their loads then go out with
+    // the atom index instead of waiting behind the branch on it
+    asm volatile("" ::"v"(fx), "v"(fy), "v"(fz));
     if (a >= 0) {
       forces[3 * a] = (double)fx * inv_scale;
       forces[3 * a + 1] = (double)fy * inv_scale;
