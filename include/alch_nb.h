@@ -59,7 +59,7 @@ enum {
   ALCH_NB_OK = 0,
   ALCH_NB_E_INVALID_ARG = 1,   /* a pointer, size, index or parameter is invalid */
   ALCH_NB_E_BOX_TOO_SMALL = 2, /* cutoff + skin exceeds half the shortest box edge */
-  ALCH_NB_E_UNSUPPORTED = 3,   /* valid request this build does not implement */
+  ALCH_NB_E_UNSUPPORTED = 3,   /* valid request that the library does not implement */
   ALCH_NB_E_CAPACITY = 4,      /* the neighbour list outgrew its workspace */
   ALCH_NB_E_HIP = 5,           /* a HIP runtime call failed (see alch_nb_last_hip_error) */
   ALCH_NB_E_NOT_BOUND = 6,     /* the context has no workspace/stream yet */
