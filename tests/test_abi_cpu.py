@@ -153,3 +153,12 @@ def test_strerror_and_misc(lib):
     assert lib.alch_nb_opes_layout(offs, 3) == 1
     assert lib.alch_nb_opes_state_size(100) == 16 + 2 * 101 + 200
     assert lib.alch_nb_opes_state_size(0) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises; there is no fallback path."""
+    from paper_2608_12691_amd import alchnb
+    monkeypatch.setattr(alchnb, "_lib", None)
+    monkeypatch.setattr(alchnb, "LIB_PATH", str(tmp_path / "libalchnb.so"))
+    with pytest.raises(ImportError):
+        alchnb.load()
