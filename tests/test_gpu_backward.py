@@ -222,3 +222,28 @@ def test_backward_param_grads_repeat_bitwise(precision):
         for a, b in zip(o, outs[0]):
             assert np.array_equal(a, b)
     assert np.any(outs[0][0] != 0.0) and np.any(outs[0][2] != 0.0)
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-9), (0, 2e-5)], ids=["fp64", "fp32"])
+def test_backward_many_types_reads_pair_table_from_hbm(precision, tol):
+    """40 atom types: the parameter pass reads the type-pair table from HBM instead of LDS."""
+    rng = np.random.Generator(np.random.PCG64(40))
+    T = 40
+    ff = S.ForceField(sigma=rng.uniform(2.5, 3.8, T), epsilon=rng.uniform(0.02, 0.25, T),
+                      charge=rng.uniform(-0.6, 0.6, T), names=["t%d" % i for i in range(T)])
+    box = S.random_tiny_system(rng, 700, 22.0, n_solute=12, n_types=T, min_dist=1.9)
+    w = S.Workload("types40", [box], ff, 9.0, 1.0, 1.0, 0.2, 0.5, np.array([0.6]), 40)
+    ctx = _ctx(w, precision)
+    pos = ctx.positions(w.systems)
+    lam = ctx.lambdas([0.6])
+    print("many types precision %d" % precision, flush=True)
+    ctx.compute(pos, lam, flags=2)
+    g = torch.ones(1, dtype=torch.float64, device=ctx.device)
+    dsig, dse, dq = (torch.zeros(T, dtype=torch.float64, device=ctx.device) for _ in range(3))
+    ctx.backward(pos, lam, g, d_sigma=dsig, d_sqrt_eps=dse, d_charge=dq)
+    torch.cuda.synchronize()
+    assert ctx.get_flags() == 0
+    ref = oracle_for(w, 0, 0.6, O.BEUTLER, param_grads=True)
+    assert _rel(dsig.cpu().numpy(), ref["d_sigma"]) < tol
+    assert _rel(dse.cpu().numpy(), ref["d_sqrt_eps"]) < tol
+    assert _rel(dq.cpu().numpy(), ref["d_charge"]) < tol
