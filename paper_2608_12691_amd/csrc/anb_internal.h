@@ -27,7 +27,7 @@ constexpr int kBarWords = kBarStride * (kBarGroups + 1);
 // the tile kernel's launch has at most kMaxWaves waves
 constexpr int kMaxWaves = 8192;
 constexpr int kRedChunks = 16;   // unit chunks per box in the final reduction
-constexpr int kAlchTileCost = 8;  // cost of a solute-solvent tile, in plain tiles
+constexpr int kAlchTileCost = 12;  // cost of a solute-solvent tile, in plain tiles (measured: 12-16 best)
 constexpr uint32_t kUnitStart = 1u << 31;  // ent_info bit: a work unit starts at this entry
 constexpr int kStrips = 8;       // search waves per super-cluster (neighbour columns dealt round-robin)
 constexpr double kKe = 332.06371;
