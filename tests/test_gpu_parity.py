@@ -320,3 +320,27 @@ def test_list_overflow_sets_flag_and_replan_recovers():
     assert res["flags"] == 0
     ref = oracle_for(w, 0, 0.5, O.BEUTLER)
     compare(to_numpy(res), [ref], w, [w.systems[0].positions], 0, _offsets(w), label="after re-plan")
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+def test_coincident_atoms_flag_overflow(precision):
+    """Two atoms of different molecules on the same point: the call completes, the force sums report
+    FLAG_FIXED_OVERFLOW and the total energy is not finite (r = 0 has no finite LJ value)."""
+    w = workload(1)
+    s = w.systems[0]
+    p = s.positions.copy()
+    a, b = 20, 50
+    assert s.molecule[a] != s.molecule[b]
+    p[b] = p[a]
+    ctx = _ctx(w, precision)
+    pos = ctx.positions(p)
+    print("coincident atoms precision %d" % precision, flush=True)
+    out = to_numpy(ctx.compute(pos, ctx.lambdas([0.5]), flags=2))
+    torch.cuda.synchronize()
+    f = ctx.get_flags()
+    assert f & 1, f
+    assert not np.isfinite(out["terms"][0, 8])
+    # the next call at valid positions is clean again
+    res, _ = _run(ctx, w, [0.5], flags=2)
+    assert res["flags"] == 0
+    compare(res, [oracle_for(w, 0, 0.5, O.BEUTLER)], w, [s.positions], precision, _offsets(w), label="after")
