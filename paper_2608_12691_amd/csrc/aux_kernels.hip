@@ -106,8 +106,8 @@ __device__ inline void pg_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// sum over the lanes that differ only in the bits of m (butterfly, the
-// same tree in every lane)
+// sum over the 8 lanes that differ only in the lane-index bits m0, m1, m2
+// (a butterfly: the same tree, and so the same result, in every lane)
 template <typename V>
 __device__ inline V lane_sum(V v, int m0, int m1, int m2) {
   v += __shfl_xor(v, m0);
