@@ -722,13 +722,15 @@ __device__ inline void grid_barrier(const Dev& d, unsigned int& gen, Serial seri
   __syncthreads();
   unsigned int* bar = d.barrier;
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned int grp = blockIdx.x % kBarGroups;
     const unsigned int n_grp = (gridDim.x - grp + kBarGroups - 1) / kBarGroups;
     const unsigned int n_top = min(gridDim.x, (unsigned int)kBarGroups);
     int last = 0;
     unsigned int* gc = bar + kBarStride * (grp + 1);
-    if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == n_grp - 1) {
+    // the arrival publishes the block's writes (release: one L2 write-back);
+    // what the block reads next is acquired by the top-level arrival (the
+    // last block) or by the acquire after the wait (all others)
+    if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == n_grp - 1) {
       __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       last = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == n_top - 1;
     }
