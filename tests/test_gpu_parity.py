@@ -123,6 +123,33 @@ def test_config2_protocol(precision):
     assert ctx.get_flags() == 0
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+def test_config2_lbf_walk(precision):
+    """The LBF schedule on the 3,000-water box: 300 calls of the walk with device-side rebuilds, checked
+    against the oracle at lambdas below the h_A onset (softened basis only), across it and near 1."""
+    w = workload(2)
+    s = w.systems[0]
+    ctx = _ctx(w, precision, O.LBF)
+    n_calls = 300
+    walk = S.perturbation_walk(s, n_calls, 0.01, seed=17)
+    checks = {0: 0.2, 120: 0.35, 180: 0.5, 299: 0.95}
+    pos = ctx.positions(walk[0])
+    lam = ctx.lambdas([0.1])
+    out = ctx.new_outputs()
+    for t in range(n_calls):
+        pos.copy_(torch.as_tensor(walk[t], device=pos.device))
+        lt = checks.get(t, 0.1 + 0.8 * t / n_calls)
+        lam.fill_(lt)
+        ctx.compute(pos, lam, flags=1, out=out)
+        if t in checks:
+            torch.cuda.synchronize()
+            print("config2 lbf call %d lambda %.3f" % (t, lt), flush=True)
+            ref = oracle_for(w, 0, lt, O.LBF, positions=walk[t])
+            compare(to_numpy(out), [ref], w, [walk[t]], precision, _offsets(w), label="cfg2 lbf t=%d" % t)
+    assert ctx.get_stats()["n_rebuilds"] >= 2
+    assert ctx.get_flags() == 0
+
+
 def test_config2_pair_set_after_walk():
     w = workload(2)
     s = w.systems[0]
