@@ -371,3 +371,30 @@ def test_coincident_atoms_flag_overflow(precision):
     res, _ = _run(ctx, w, [0.5], flags=2)
     assert res["flags"] == 0
     compare(res, [oracle_for(w, 0, 0.5, O.BEUTLER)], w, [s.positions], precision, _offsets(w), label="after")
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("schedule", [O.BEUTLER, O.LBF], ids=["beutler", "lbf"])
+@pytest.mark.parametrize("alpha", [0.2, 0.0], ids=["dsf", "sf"])
+def test_hard_truncation_and_plain_shifted_force(precision, schedule, alpha):
+    """No LJ switch (the kernels without the switch) and, with alpha = 0, plain shifted-force Coulomb."""
+    w1 = workload(1)
+    w = S.Workload("cfg1-hard", w1.systems, w1.ff, w1.cutoff, w1.skin, 0.0, alpha, w1.sc_alpha, w1.lambdas, w1.seed)
+    ctx = _ctx(w, precision, schedule)
+    for lam in (0.3, 0.8):
+        print("hard truncation precision=%d schedule=%d alpha=%.1f lambda=%.1f" % (precision, schedule, alpha, lam),
+              flush=True)
+        res, pos = _run(ctx, w, [lam], flags=2)
+        assert res["flags"] == 0
+        ref = oracle_for(w, 0, lam, schedule, param_grads=True)
+        compare(res, [ref], w, pos, precision, _offsets(w), label="hard lam=%g" % lam)
+        # the parameter pass without the switch
+        T = ctx.n_types
+        dsig, dq = (torch.zeros(T, dtype=torch.float64, device=ctx.device) for _ in range(2))
+        ctx.backward(ctx.positions(pos[0]), ctx.lambdas([lam]), torch.ones(1, dtype=torch.float64, device=ctx.device),
+                     d_sigma=dsig, d_charge=dq)
+        torch.cuda.synchronize()
+        tol = 1e-9 if precision == 1 else 2e-5
+        for got, want in ((dsig, ref["d_sigma"]), (dq, ref["d_charge"])):
+            g = got.cpu().numpy()
+            assert np.abs(g - want).max() <= tol * np.abs(want).max()
