@@ -398,3 +398,38 @@ def test_hard_truncation_and_plain_shifted_force(precision, schedule, alpha):
         for got, want in ((dsig, ref["d_sigma"]), (dq, ref["d_charge"])):
             g = got.cpu().numpy()
             assert np.abs(g - want).max() <= tol * np.abs(want).max()
+
+
+def _orthorhombic_box(seed, L=(22.0, 26.0, 31.0)):
+    """Atoms on a jittered grid (>= 2.6 A apart, liquid-like packing without bonded contacts) in an
+    orthorhombic box with three different edges."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    L = np.asarray(L)
+    n = np.floor(L / 3.0).astype(int)
+    g = np.stack(np.meshgrid(*[np.arange(k) for k in n], indexing="ij"), -1).reshape(-1, 3).astype(float)
+    pos = (g + 0.5) * (L / n) + rng.uniform(-0.2, 0.2, g.shape)
+    w1 = workload(1)
+    types = rng.integers(0, w1.ff.n_types, len(pos)).astype(np.int32)
+    sol = np.zeros(len(pos), np.uint8)
+    sol[rng.choice(len(pos), 10, replace=False)] = 1
+    box = S.System(positions=pos, types=types, is_solute=sol, exclusions=np.zeros((0, 2), np.int32), box=L,
+                   molecule=np.arange(len(pos), dtype=np.int32))
+    return S.Workload("ortho", [box], w1.ff, 9.0, 1.0, 1.0, 0.2, 0.5, np.array([0.4]), seed)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+def test_orthorhombic_box_pairs_and_parity(precision):
+    """Edges 22 x 26 x 31 A: the exported pair set equals the oracle's and the results match it."""
+    w = _orthorhombic_box(31)
+    s = w.systems[0]
+    ctx = _ctx(w, precision)
+    pos = ctx.positions(w.systems)
+    print("orthorhombic box precision %d atoms %d" % (precision, s.n_atoms), flush=True)
+    ctx.build_list(pos)
+    got = ctx.export_pairs()
+    ref_pairs = O.pair_set(s.positions, s.exclusions, s.box, w.cutoff + w.skin)
+    assert np.array_equal(got, ref_pairs)
+    for lam in (0.4, 0.9):
+        res, p = _run(ctx, w, [lam], flags=2)
+        assert res["flags"] == 0
+        compare(res, [oracle_for(w, 0, lam, O.BEUTLER)], w, p, precision, _offsets(w), label="ortho lam=%g" % lam)
