@@ -433,3 +433,46 @@ def test_orthorhombic_box_pairs_and_parity(precision):
         res, p = _run(ctx, w, [lam], flags=2)
         assert res["flags"] == 0
         compare(res, [oracle_for(w, 0, lam, O.BEUTLER)], w, p, precision, _offsets(w), label="ortho lam=%g" % lam)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+def test_box_at_the_size_limit_and_many_boxes(precision):
+    """A 20 A box with cutoff + skin = 10 A (exactly half the edge) and 40 small boxes in one call."""
+    rng = np.random.Generator(np.random.PCG64(2020))
+    w1 = workload(1)
+    edge = S.random_tiny_system(rng, 260, 20.0, n_solute=6, n_types=w1.ff.n_types, min_dist=2.2)
+    w = S.Workload("edge", [edge], w1.ff, 9.0, 1.0, 1.0, 0.2, 0.5, np.array([0.45]), 2020)
+    ctx = _ctx(w, precision)
+    pos = ctx.positions(w.systems)
+    print("box at the limit precision %d" % precision, flush=True)
+    ctx.build_list(pos)
+    assert np.array_equal(ctx.export_pairs(), O.pair_set(edge.positions, edge.exclusions, edge.box, 10.0))
+    res, p = _run(ctx, w, [0.45], flags=2)
+    assert res["flags"] == 0
+    compare(res, [oracle_for(w, 0, 0.45, O.BEUTLER)], w, p, precision, _offsets(w), label="edge")
+    # 40 boxes of 30-90 atoms at lambda_k = k/39
+    boxes = [S.random_tiny_system(rng, int(n), 20.0, n_solute=3, n_types=w1.ff.n_types, min_dist=2.6)
+             for n in rng.integers(30, 90, 40)]
+    lams = np.linspace(0.0, 1.0, 40)
+    wm = S.Workload("many", boxes, w1.ff, 9.0, 1.0, 1.0, 0.2, 0.5, lams, 2021)
+    cm = _ctx(wm, precision)
+    print("40 boxes precision %d" % precision, flush=True)
+    res, p = _run(cm, wm, list(lams), flags=2)
+    assert res["flags"] == 0
+    refs = [oracle_for(wm, k, lams[k], O.BEUTLER) for k in range(40)]
+    if precision == 1:
+        compare(res, refs, wm, p, precision, _offsets(wm), label="many boxes")
+        return
+    # FP32: in boxes of 30-90 atoms with 3 solute atoms, dU/dlambda cancels down to 0.3-4% of
+    # sum |du/dlambda|, and the FP32 rounding of the pair terms (measured up to 4.5e-7 of that sum)
+    # is then above 1e-6 of |dU/dlambda|: here it is measured against sum |du/dlambda|.  Energy terms
+    # made of a few contact pairs carry their per-pair FP32 rounding (measured 1.0e-6 of sum |u|):
+    # checked at 1e-5 of sum |u| here
+    from parity import energy_error, force_error
+    off = _offsets(wm)
+    for k, ref in enumerate(refs):
+        assert force_error(res["forces"][off[k]:off[k + 1]], ref["forces"]) <= TOL[0]["force"], k
+        sc = ref["abs_terms"][9]
+        assert abs(res["dudl"][k] - ref["terms"][9]) <= TOL[0]["dudl"] * sc, k
+        assert max(energy_error(res["terms"][k, j], ref["terms"][j], ref["abs_terms"][j]) for j in range(10)) \
+            <= 10 * TOL[0]["energy"], k
