@@ -185,9 +185,11 @@ def aux_paths(torch, w, traj, lams, W, K):
         fwd(t)
         ctx.backward(traj[t], lams[t], g, d_pos=d_pos, d_lambda=d_lam, d_sigma=d_sig, d_sqrt_eps=d_se, d_charge=d_q)
 
+    cv_out = ctx.dihedrals(traj[0], idx, mass_inv=minv, s=sv, kappa=kap)
+
     def cvs_opes(t):
         fwd(t)
-        ctx.dihedrals(traj[t], idx, mass_inv=minv, s=sv, kappa=kap, forces=out["forces"])
+        ctx.dihedrals(traj[t], idx, mass_inv=minv, s=sv, kappa=kap, forces=out["forces"], out=cv_out)
         ctx.opes_update(st, out["dudl"], lam_out, deposit=(t % 20 == 0))
 
     ms = {}

@@ -276,13 +276,20 @@ class Context:
                                        ctypes.c_void_p(grad_energy.data_ptr()), ctypes.byref(g))
         self._check("alch_nb_backward", st)
 
-    def dihedrals(self, pos, idx, mass_inv=None, s=None, kappa=None, forces=None):
+    def dihedrals(self, pos, idx, mass_inv=None, s=None, kappa=None, forces=None, out=None):
+        """Dihedral CVs; `out` (a dict returned by an earlier call with the same n and options) is
+        reused instead of new zeroed outputs (a CV with an invalid index then keeps its old values)."""
         torch = self.torch
         n = int(idx.shape[0])
-        xi = torch.zeros(n, dtype=torch.float64, device=self.device)
-        dxi = torch.zeros((n, 4, 3), dtype=torch.float64, device=self.device)
-        msum = torch.zeros(n, dtype=torch.float64, device=self.device) if mass_inv is not None else None
-        u = torch.zeros(1, dtype=torch.float64, device=self.device) if s is not None else None
+        if out is not None:
+            xi, dxi, msum, u = out["xi"], out["dxi"], out["msum"], out["u_dafed"]
+            assert xi.shape == (n,) and (msum is not None) == (mass_inv is not None)
+            assert (u is not None) == (s is not None)
+        else:
+            xi = torch.zeros(n, dtype=torch.float64, device=self.device)
+            dxi = torch.zeros((n, 4, 3), dtype=torch.float64, device=self.device)
+            msum = torch.zeros(n, dtype=torch.float64, device=self.device) if mass_inv is not None else None
+            u = torch.zeros(1, dtype=torch.float64, device=self.device) if s is not None else None
         st = self.lib.alch_nb_dihedrals(self.ctx, ctypes.c_void_p(pos.data_ptr()), n,
                                         ctypes.c_void_p(idx.data_ptr()), ctypes.c_void_p(xi.data_ptr()),
                                         ctypes.c_void_p(dxi.data_ptr()), _addr(mass_inv), _addr(msum), _addr(s),

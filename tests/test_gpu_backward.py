@@ -247,3 +247,21 @@ def test_backward_many_types_reads_pair_table_from_hbm(precision, tol):
     assert _rel(dsig.cpu().numpy(), ref["d_sigma"]) < tol
     assert _rel(dse.cpu().numpy(), ref["d_sqrt_eps"]) < tol
     assert _rel(dq.cpu().numpy(), ref["d_charge"]) < tol
+
+
+def test_dihedrals_reuse_outputs():
+    """The binding's output reuse gives the same CVs as fresh outputs."""
+    w, idx = _peptide_box()
+    ctx = _ctx(w, 0)
+    pos = ctx.positions(w.systems)
+    it = torch.tensor(idx, device=ctx.device)
+    minv = torch.ones(ctx.N, dtype=torch.float64, device=ctx.device)
+    sv = torch.tensor([0.1, 0.2, -3.0, 2.0], dtype=torch.float64, device=ctx.device)
+    kap = torch.full((4,), 250.0, dtype=torch.float64, device=ctx.device)
+    a = ctx.dihedrals(pos, it, mass_inv=minv, s=sv, kappa=kap)
+    b = ctx.dihedrals(pos + 0.01, it, mass_inv=minv, s=sv, kappa=kap)
+    c = ctx.dihedrals(pos, it, mass_inv=minv, s=sv, kappa=kap, out=b)
+    torch.cuda.synchronize()
+    assert c["xi"] is b["xi"]
+    for k in ("xi", "dxi", "msum", "u_dafed"):
+        assert torch.equal(a[k], c[k]), k
