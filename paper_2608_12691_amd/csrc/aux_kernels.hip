@@ -22,6 +22,7 @@
 #include "anb_internal.h"
 #include "anb_kernels.h"
 #include "erfc_coeffs.h"
+#include "lane_ops.h"
 
 namespace anb {
 
@@ -248,27 +249,24 @@ __global__ void __launch_bounds__(kBlk) k_pgrad(Dev d, PotConsts pc, const doubl
         bj2 += wq * (R)q_t[ti];
       }
       // the j-atom's sums over il, weighted by the box's upstream gradient
-      const double vj0 = g * (double)lane_sum(bj0, 1, 2, 4);
-      const double vj1 = g * (double)lane_sum(bj1, 1, 2, 4);
-      const double vj2 = g * (double)lane_sum(bj2, 1, 2, 4);
+      const double vj0 = g * (double)red8(bj0);
+      const double vj1 = g * (double)red8(bj1);
+      const double vj2 = g * (double)red8(bj2);
       if (il == 0) {
         add_fixed(acc0 + jsl, vj0, scale, d.flags);
         add_fixed(acc1 + jsl, vj1, scale, d.flags);
         add_fixed(acc2 + jsl, vj2, scale, d.flags);
       }
     }
-    // the i-atoms' sums over jl
-#pragma unroll
-    for (int c = 0; c < kScCl; ++c) {
-      const double v0 = g * (double)lane_sum(ai0[c], 8, 16, 32);
-      const double v1 = g * (double)lane_sum(ai1[c], 8, 16, 32);
-      const double v2 = g * (double)lane_sum(ai2[c], 8, 16, 32);
-      if (jl == 0) {
-        const int isl = s * kSc + c * kCl + il;
-        add_fixed(acc0 + isl, v0, scale, d.flags);
-        add_fixed(acc1 + isl, v1, scale, d.flags);
-        add_fixed(acc2 + isl, v2, scale, d.flags);
-      }
+    // the i-atoms' sums over jl, reduce-scattered so that lane l holds slot
+    // s * 64 + l (one atomic per lane and component)
+    {
+      const bool odd8 = (lane & 8) != 0;
+      const R v0 = scatter_jl(ai0, odd8), v1 = scatter_jl(ai1, odd8), v2 = scatter_jl(ai2, odd8);
+      const int isl = s * kSc + lane;
+      add_fixed(acc0 + isl, g * (double)v0, scale, d.flags);
+      add_fixed(acc1 + isl, g * (double)v1, scale, d.flags);
+      add_fixed(acc2 + isl, g * (double)v2, scale, d.flags);
     }
   }
 }
