@@ -342,7 +342,7 @@ __global__ void k_backward_finish(Dev d, double inv_scale, const double* __restr
   if (!d_pos) return;
   const int slots = d.sc_cap * kSc;
   for (int a = t; a < d.n_atoms; a += gridDim.x * kBlk) {
-    const double g = g_energy[d.grids[d.atom_grid[a]].replica];
+    const double g = g_energy[d.atom_rep[a]];
     const int sl = d.atom_slot[a];
     for (int c = 0; c < 3; ++c) d_pos[3 * a + c] -= g * (double)(long long)d.ffix[c * slots + sl] * inv_scale;
   }
