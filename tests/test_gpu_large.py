@@ -56,6 +56,33 @@ def test_config3_forward_backward_three_lambdas(precision):
         assert _rel(dq.cpu().numpy(), ref["d_charge"]) < ptol
 
 
+@pytest.mark.parametrize("precision", [1, 0], ids=["fp64", "fp32"])
+def test_config3_lbf_forward_and_parameter_pass(precision):
+    """The LBF schedule on the octanol box (flexible solute with bond-graph exclusions) at lambdas on
+    both sides of the h_A onset: forward and per-type gradients against the full oracle."""
+    from paper_2608_12691_amd import alchnb
+    w = workload(3)
+    s = w.systems[0]
+    ctx = alchnb.from_workload(w, precision=precision, schedule=O.LBF)
+    pos = ctx.positions(w.systems)
+    T = ctx.n_types
+    g = torch.ones(1, dtype=torch.float64, device=ctx.device)
+    ptol = 1e-9 if precision == 1 else 3e-5
+    for lam in (0.25, 0.7):
+        print("config3 lbf precision %d lambda %.2f" % (precision, lam), flush=True)
+        lt = ctx.lambdas([lam])
+        res = to_numpy(ctx.compute_checked(pos, lt, flags=2))
+        assert res["flags"] == 0
+        ref = oracle_for(w, 0, lam, O.LBF, param_grads=True)
+        compare(res, [ref], w, [s.positions], precision, np.array([0, s.n_atoms]), label="cfg3 lbf lam=%g" % lam)
+        dsig, dse, dq = (torch.zeros(T, dtype=torch.float64, device=ctx.device) for _ in range(3))
+        ctx.backward(pos, lt, g, d_sigma=dsig, d_sqrt_eps=dse, d_charge=dq)
+        torch.cuda.synchronize()
+        assert _rel(dsig.cpu().numpy(), ref["d_sigma"]) < ptol
+        assert _rel(dse.cpu().numpy(), ref["d_sqrt_eps"]) < ptol
+        assert _rel(dq.cpu().numpy(), ref["d_charge"]) < ptol
+
+
 def test_config3_fp64_energy_fd_in_type_parameters():
     """Central differences (h = 1e-4) of the GPU FP64 energy in the parameters
     of the octanol carbon, the hydroxyl oxygen and two solute types."""
