@@ -241,15 +241,17 @@ def test_autotune_keeps_parity_and_caches(tmp_path, monkeypatch):
 
 
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
-def test_config4_batched_replicas(precision):
-    """16 boxes of 2,000-12,000 atoms at lambda_k = k/15 in one launch; sampled boxes vs the oracle."""
+@pytest.mark.parametrize("schedule", [O.BEUTLER, O.LBF], ids=["beutler", "lbf"])
+def test_config4_batched_replicas(precision, schedule):
+    """16 boxes of 2,000-12,000 atoms at lambda_k = k/15 in one launch; sampled boxes vs the oracle
+    (each box with its own lambda factors, for both schedules)."""
     w = workload(4)
-    ctx = _ctx(w, precision)
+    ctx = _ctx(w, precision, schedule)
     res, pos = _run(ctx, w, w.lambdas, flags=2)
     off = _offsets(w)
     for k in (0, 5, 10, 15):
         sub = {kk: (v[off[k]:off[k + 1]] if kk == "forces" else v[k:k + 1]) for kk, v in res.items() if kk != "flags"}
-        ref = oracle_for(w, k, w.lambdas[k], O.BEUTLER)
+        ref = oracle_for(w, k, w.lambdas[k], schedule)
         one = S.Workload(w.name, [w.systems[k]], w.ff, w.cutoff, w.skin, w.switch_width, w.dsf_alpha, w.sc_alpha,
                          w.lambdas[k:k + 1], w.seed)
         compare(sub, [ref], one, [w.systems[k].positions], precision, np.array([0, off[k + 1] - off[k]]),
