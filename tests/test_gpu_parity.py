@@ -150,6 +150,36 @@ def test_config2_lbf_walk(precision):
     assert ctx.get_flags() == 0
 
 
+def test_config2_long_walk_many_rebuilds():
+    """10,000 calls of a walk with N(0, 0.003 A) steps (about 0.3 A rms per coordinate at the end, as far
+    as the 1,000-call protocol drifts; an uncorrelated walk of all atoms that goes much further brings
+    non-bonded atoms into contact and overflows the fixed-point forces, as it should): no flags, the
+    device-side rebuilds (eight for this seed), and the last call and the list built at its positions
+    match the oracle."""
+    w = workload(2)
+    s = w.systems[0]
+    ctx = _ctx(w, 0)
+    n_calls = 10000
+    rng = np.random.Generator(np.random.PCG64(2626))
+    x = torch.as_tensor(s.positions, dtype=torch.float64, device="cuda")
+    steps = torch.as_tensor(rng.normal(0.0, 0.003, (n_calls, s.n_atoms, 3)), device="cuda")
+    lam = ctx.lambdas([0.6])
+    out = ctx.new_outputs()
+    print("config2 long walk: %d calls" % n_calls, flush=True)
+    for t in range(n_calls):
+        x += steps[t]
+        ctx.compute(x, lam, flags=1, out=out)
+    torch.cuda.synchronize()
+    st = ctx.get_stats()
+    assert ctx.get_flags() == 0
+    assert st["n_rebuilds"] >= 5, st["n_rebuilds"]
+    last = x.cpu().numpy()
+    res = to_numpy(out)
+    compare(res, [oracle_for(w, 0, 0.6, O.BEUTLER, positions=last)], w, [last], 0, _offsets(w), label="long walk")
+    ctx.build_list(x)
+    assert np.array_equal(ctx.export_pairs(), O.pair_set(last, s.exclusions, s.box, w.cutoff + w.skin))
+
+
 def test_config2_pair_set_after_walk():
     w = workload(2)
     s = w.systems[0]
