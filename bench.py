@@ -101,23 +101,59 @@ def count_pairs(ctx, traj, lams, W, K, torch):
     return int(acc.item())
 
 
-def cpu_baseline(w, traj_np, lams_np, W, sample_calls):
+def plan_frames(W, K, cpu_calls):
+    """Frames of the walk the run needs: the W warm-up and K timed calls of
+    the GPU legs, and the CPU sample, which reads calls W .. W+cpu_calls-1 of
+    the same walk (a sample longer than the timed region gets its own frames)."""
+    if W < 0 or K < 1 or cpu_calls < 0:
+        raise ValueError("warmup >= 0, steps >= 1 and cpu sample >= 0 required")
+    return W + max(K, cpu_calls)
+
+
+def _oracle_leg(w, traj_np, lams_np, first, max_calls, budget_s, threads):
     import oracle as O
     s = w.systems[0]
     P = O.Params.of(w)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    O.evaluate(traj_np[W], s.types, s.is_solute, s.exclusions, s.box, w.ff.sigma, w.ff.epsilon, w.ff.charge, P,
-               lams_np[W], n_threads=threads)  # load and warm up
-    n = 0
+    ev = lambda t: O.evaluate(traj_np[t], s.types, s.is_solute, s.exclusions, s.box, w.ff.sigma, w.ff.epsilon,
+                              w.ff.charge, P, lams_np[t], n_threads=threads)
+    last = min(first + max_calls, len(traj_np))
+    if last <= first:
+        raise ValueError("no frame left for the CPU sample (first %d, frames %d)" % (first, len(traj_np)))
+    ev(first)  # library load and cache warm-up, untimed
+    n = calls = 0
     t0 = time.perf_counter()
-    for t in range(W, W + sample_calls):
-        r = O.evaluate(traj_np[t], s.types, s.is_solute, s.exclusions, s.box, w.ff.sigma, w.ff.epsilon,
-                       w.ff.charge, P, lams_np[t], n_threads=threads)
-        n += r["n_pairs"]
+    for t in range(first, last):
+        n += ev(t)["n_pairs"]
+        calls += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
     dt = time.perf_counter() - t0
     return dict(value=n / dt, unit="pair-evals/s", cores=threads, kind="oracle",
-                sample="%d consecutive calls of the same walk (calls %d-%d), full O(N^2) FP64 evaluation each, "
-                       "%.1f s" % (sample_calls, W, W + sample_calls - 1, dt))
+                sample="%d consecutive calls of the timed walk (calls %d-%d), each a full O(N^2) FP64 evaluation "
+                       "of the 8,973-atom box, %.2f s wall" % (calls, first, first + calls - 1, dt))
+
+
+def host_threads():
+    """Threads the oracle runs on: OMP_NUM_THREADS when set, else the CPUs this process may use."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.strip().isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w, traj_np, lams_np, W, max_calls, budget_s=12.0, budget_1core_s=10.0):
+    """The oracle timed on the host: all threads, then one, each on a bounded
+    sample of the calls the GPU timed (stopping at max_calls calls or once the
+    time budget is spent)."""
+    rec = _oracle_leg(w, traj_np, lams_np, W, max_calls, budget_s, host_threads())
+    try:
+        rec["single_core"] = _oracle_leg(w, traj_np, lams_np, W, max_calls, budget_1core_s, 1)
+    except Exception as e:  # the all-core figure stands on its own
+        rec["single_core"] = {"error": repr(e)}
+    return rec
 
 
 def batched_vs_single(torch, steps, warmup, graph):
@@ -214,6 +250,54 @@ def aux_paths(torch, w, traj, lams, W, K):
             "device_flags": flags}
 
 
+def rebuild_cost(ctx, traj, lams, torch, reps=10):
+    """Extra time of a call that rebuilds the list: forced rebuilds against
+    plain calls at the same positions (HIP events on the bound stream)."""
+    from paper_2608_12691_amd import alchnb
+    pos, lam = traj[0], lams[0]
+    out = ctx.new_outputs()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ctx.compute(pos, lam, flags=alchnb.FORCE_REBUILD, out=out)
+    ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
+    ev[0].record()
+    for _ in range(reps):
+        ctx.compute(pos, lam, flags=alchnb.FORCE_REBUILD, out=out)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(reps):
+        ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
+    ev[3].record()
+    torch.cuda.synchronize()
+    forced = ev[0].elapsed_time(ev[1]) / reps
+    plain = ev[2].elapsed_time(ev[3]) / reps
+    return 1e3 * (forced - plain), 1e3 * plain
+
+
+def rebuild_rate(ctx, s, torch, n_calls, seed):
+    """Calls per device-side rebuild over the call protocol's walk (untimed):
+    a fresh build, then n_calls steps of N(0, 0.01 A) with automatic rebuilds."""
+    from paper_2608_12691_amd import alchnb, systems
+    walk = torch.as_tensor(systems.perturbation_walk(s, n_calls + 1, 0.01, seed=seed), dtype=torch.float64,
+                           device="cuda:0")
+    lam = torch.full((1,), 0.5, dtype=torch.float64, device="cuda:0")
+    out = ctx.new_outputs(forces=False)
+    ctx.compute(walk[0], lam, flags=alchnb.FORCE_REBUILD, out=out)
+    n0 = ctx.get_stats()["n_rebuilds"]
+    for t in range(1, n_calls + 1):
+        ctx.compute(walk[t], lam, flags=alchnb.AUTO_REBUILD, out=out)
+    n = ctx.get_stats()["n_rebuilds"] - n0
+    return n_calls / n if n else float("inf"), int(n)
+
+
+def optional(line, key, fn):
+    """Run an optional leg; a failure is recorded in the line instead of losing it."""
+    try:
+        line[key] = fn()
+    except Exception as e:  # noqa: BLE001 - reported, never silent
+        log("leg %s failed: %r" % (key, e))
+        line[key] = {"error": repr(e)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,12 +307,15 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-calls", type=int, default=48)
+    ap.add_argument("--cpu-calls", type=int, default=200, help="at most this many oracle calls per CPU leg")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="time budget of the all-core oracle leg")
+    ap.add_argument("--cpu-seconds-1core", type=float, default=10.0, help="time budget of the one-core leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--no-aux", action="store_true")
     ap.add_argument("--aux-steps", type=int, default=300)
+    ap.add_argument("--rebuild-calls", type=int, default=1000, help="walk length for the calls-per-rebuild figure")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="after the run, copy a device buffer of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -243,16 +330,18 @@ def main():
         from paper_2608_12691_amd import build
         build.build()
     W, K = args.warmup, args.steps
+    cpu_calls = 0 if args.no_cpu_baseline else args.cpu_calls
+    n_frames = plan_frames(W, K, cpu_calls)
     w = systems.make_config(2)
     s = w.systems[0]
-    log("workload", w.name, "atoms", s.n_atoms, "box", s.box[0])
-    traj_np = systems.perturbation_walk(s, W + K, 0.01, seed=systems.config_seed(2) + 500)
-    lams_np = systems.lambda_draws(W + K, seed=systems.config_seed(2) + 501)
+    log("workload", w.name, "atoms", s.n_atoms, "box", s.box[0], "frames", n_frames)
+    traj_np = systems.perturbation_walk(s, n_frames, 0.01, seed=systems.config_seed(2) + 500)
+    lams_np = systems.lambda_draws(n_frames, seed=systems.config_seed(2) + 501)
     dev = torch.device("cuda:0")
     # all work on one non-default stream (graph capture needs one)
     torch.cuda.set_stream(torch.cuda.Stream(dev))
-    traj = torch.as_tensor(traj_np, dtype=torch.float64, device=dev)
-    lams = torch.as_tensor(lams_np, dtype=torch.float64, device=dev).reshape(-1, 1)
+    traj = torch.as_tensor(traj_np[: W + K], dtype=torch.float64, device=dev)
+    lams = torch.as_tensor(lams_np[: W + K], dtype=torch.float64, device=dev).reshape(-1, 1)
 
     res = {}
     for prec in ([alchnb.FP32_FIXED] if args.no_fp64 else [alchnb.FP32_FIXED, alchnb.FP64]):
@@ -270,9 +359,17 @@ def main():
         # final call's outputs for cross-precision errors
         ctx.compute(pos_last, lam_last, flags=alchnb.AUTO_REBUILD, out=out)
         torch.cuda.synchronize()
-        res[prec] = dict(elapsed=elapsed, tile_ms=tile_ms, n_pairs=n_pairs, rebuilds=rebuilds, flags=flags,
-                         stats=stats, forces=out["forces"].cpu().numpy(), dudl=float(out["dudl"][0]),
-                         terms=out["terms"][0].cpu().numpy())
+        r = dict(elapsed=elapsed, tile_ms=tile_ms, n_pairs=n_pairs, rebuilds=rebuilds, flags=flags,
+                 stats=stats, forces=out["forces"].cpu().numpy(), dudl=float(out["dudl"][0]),
+                 terms=out["terms"][0].cpu().numpy())
+        if prec == alchnb.FP32_FIXED:
+            try:
+                r["rebuild_us"], r["plain_call_us"] = rebuild_cost(ctx, traj, lams, torch)
+                r["calls_per_rebuild"], r["rebuilds_in_walk"] = rebuild_rate(ctx, s, torch, args.rebuild_calls,
+                                                                             systems.config_seed(2) + 502)
+            except Exception as e:  # noqa: BLE001 - reported in the line
+                r["rebuild_error"] = repr(e)
+        res[prec] = r
         log("precision", prec, "elapsed %.4f s" % elapsed, "tile %.2f us" % (1e3 * tile_ms if tile_ms else -1),
             "pairs/call %.0f" % (n_pairs / K), "rebuilds", rebuilds, "flags", flags)
         ctx.close()
@@ -287,7 +384,8 @@ def main():
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32, "traffic": measured_traffic("tile_fp32_water3000_traffic.json"),
                 "kernel": "k_tile<float, Beutler, switch>", "avg_launch_us": r32["tile_ms"] * 1e3,
-                "flop_per_pair": fpp, "pairs_per_launch": pairs_per_call,
+                "flop_per_pair": fpp, "flop_basis": "algorithmic count of the plain pair's defining formulas",
+                "pairs_per_launch": pairs_per_call,
                 "tiles_per_launch": r32["stats"]["n_tiles"],
                 "entries_per_launch": r32["stats"]["n_entries"],
                 "units_per_launch": r32["stats"]["n_units"],
@@ -305,6 +403,18 @@ def main():
                    "rebuilds_in_timed_region": r32["rebuilds"], "variant": r32["stats"]["variant"]},
         "roofline": roof,
     }
+    if "calls_per_rebuild" in r32:
+        # the headline's K steps may hold fewer (or more) rebuilds than the
+        # protocol's rate: the amortised figure charges exactly that rate
+        expect = K / r32["calls_per_rebuild"]
+        amort_s = r32["elapsed"] + (expect - r32["rebuilds"]) * r32["rebuild_us"] * 1e-6
+        line["rebuild"] = {"rebuild_us": r32["rebuild_us"], "plain_call_us": r32["plain_call_us"],
+                           "calls_per_rebuild": r32["calls_per_rebuild"],
+                           "rebuilds_in_walk": r32["rebuilds_in_walk"], "walk_calls": args.rebuild_calls,
+                           "value_amortised": r32["n_pairs"] / amort_s,
+                           "ms_per_step_amortised": 1e3 * amort_s / K}
+    elif "rebuild_error" in r32:
+        line["rebuild"] = {"error": r32["rebuild_error"]}
     if alchnb.FP64 in res:
         r64 = res[alchnb.FP64]
         v64 = r64["n_pairs"] / r64["elapsed"]
@@ -318,11 +428,12 @@ def main():
             "energy_rel": float(abs(r32["terms"][8] - r64["terms"][8]) / max(abs(r64["terms"][8]), 1e-300))}
     line["device_flags"] = {"fp32": r32["flags"], "fp64": res.get(alchnb.FP64, {}).get("flags")}
     if not args.no_batched:
-        line["hrex16"] = batched_vs_single(torch, args.batched_steps, 20, args.mode == "graph")
+        optional(line, "hrex16", lambda: batched_vs_single(torch, args.batched_steps, 20, args.mode == "graph"))
     if not args.no_aux:
-        line["aux"] = aux_paths(torch, w, traj, lams, min(W, 20), min(K, args.aux_steps))
+        optional(line, "aux", lambda: aux_paths(torch, w, traj, lams, min(W, 20), min(K, args.aux_steps)))
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, traj_np, lams_np, W, args.cpu_calls)
+        optional(line, "cpu_baseline", lambda: cpu_baseline(w, traj_np, lams_np, W, cpu_calls, args.cpu_seconds,
+                                                            args.cpu_seconds_1core))
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

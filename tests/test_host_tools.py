@@ -69,3 +69,50 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def _bench_module():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_bench_frame_plan_covers_every_leg():
+    """The walk holds the warm-up, the timed calls and the CPU sample at the
+    driver's arguments (--steps 20 --warmup 5) and at the defaults."""
+    b = _bench_module()
+    assert b.plan_frames(5, 20, 200) == 205
+    assert b.plan_frames(50, 1000, 200) == 1050
+    assert b.plan_frames(5, 20, 0) == 25
+    with pytest.raises(ValueError):
+        b.plan_frames(5, 0, 10)
+
+
+def test_bench_cpu_baseline_on_a_short_walk():
+    """The oracle legs stay inside the frames they are given (a 25-frame walk,
+    W = 5: at most 20 calls) and report both thread counts."""
+    from paper_2608_12691_amd import systems
+    b = _bench_module()
+    w = systems.make_config(2)
+    s = w.systems[0]
+    W, K = 5, 20
+    traj = systems.perturbation_walk(s, W + K, 0.01, seed=7)
+    lams = systems.lambda_draws(W + K, seed=8)
+    rec = b.cpu_baseline(w, traj, lams, W, 200, budget_s=0.2, budget_1core_s=0.2)
+    assert rec["kind"] == "oracle" and rec["unit"] == "pair-evals/s" and rec["value"] > 0
+    assert rec["cores"] == b.host_threads() and rec["single_core"]["cores"] == 1
+    assert rec["single_core"]["value"] > 0
+    # a sample that starts past the last frame is an error, not an index fault
+    with pytest.raises(ValueError):
+        b._oracle_leg(w, traj, lams, W + K, 10, 1.0, 1)
+
+
+def test_bench_optional_leg_failure_is_recorded():
+    b = _bench_module()
+    line = {}
+    b.optional(line, "leg", lambda: 1 / 0)
+    assert "ZeroDivisionError" in line["leg"]["error"]
+    b.optional(line, "ok", lambda: 3)
+    assert line["ok"] == 3
