@@ -105,3 +105,62 @@ def test_oracle_reproduces_golden():
         F = r["forces"][atoms]
         Fg = np.asarray(c["forces"])
         assert np.sqrt(np.sum((F - Fg) ** 2) / np.sum(Fg * Fg)) < 1e-12
+
+
+# ---------------------------------------------------------------- closed forms (mpmath, no oracle)
+
+CLOSED = _load("closed_forms.json")
+
+
+def test_closed_form_fixture_is_reproduced():
+    """The stored table is what its committed script computes (no oracle involved)."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("mcf", os.path.join(GOLDEN, "make_closed_forms.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    fresh = m.table()
+    assert len(fresh["pairs"]) == len(CLOSED["pairs"])
+    for a, b in zip(fresh["pairs"], CLOSED["pairs"]):
+        assert (a["form"], a["r"], a["lam"]) == (b["form"], b["r"], b["lam"])
+        assert np.allclose(a["values"], b["values"], rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("form", ["beutler", "lbf", "plain"])
+def test_oracle_single_pair_against_closed_forms(form):
+    """Energy, -du/dr, the left du/dlambda and the parameter derivatives of
+    one pair at interior lambda (Beutler 1/2 < lambda < 1 included: the
+    electrostatic stage) and inside the u_cap core, against 40-digit values."""
+    sched = O.LBF if form == "lbf" else O.BEUTLER
+    prm = CLOSED["params"]
+    P = O.Params(prm["cutoff"], prm["switch_width"], prm["dsf_alpha"], prm["sc_alpha"], sched)
+    rows = [r for r in CLOSED["pairs"] if r["form"] == form]
+    assert rows
+    for row in rows:
+        got = O.pair_probe(row["r"], prm["sigma"], prm["epsilon"], prm["qq"], form != "plain", P, row["lam"])
+        want = np.asarray(row["values"])
+        scale = np.maximum(np.abs(want), 1e-9 * np.abs(want).max())
+        assert np.all(np.abs(got - want) <= 1e-10 * scale), (row, got)
+
+
+def test_lbf_switches_against_closed_forms():
+    for row in CLOSED["lbf_switches"]["rows"]:
+        got = O.lbf_switches(row["lam"])
+        assert np.allclose(got, row["values"], rtol=1e-12, atol=1e-15), (row["lam"], got)
+
+
+def test_survey_two_particle_values_are_in_the_fixture():
+    """The Beutler values at r = 3.5 A for lambda = 0.25, 0.5, 0.75, 1 and
+    the LBF values at r = 2.0 A (lambda = 1/2, inside the cap) and 3.5 A
+    (lambda = 3/4), as (u, -du/dr, du/dlambda)."""
+    want = {("beutler", 3.5, 0.25): (-0.0599775149151449, 0.00354216174004655, -0.238703144380784),
+            ("beutler", 3.5, 0.5): (-0.116604573669458, 0.0808486142144937, -0.205661724322461),
+            ("beutler", 3.5, 0.75): (-4.33560631530104, -3.14116426025866, -16.8760069665263),
+            ("beutler", 3.5, 1.0): (-8.55460805693263, -6.36317713473181, -16.8760069665263),
+            ("lbf", 2.0, 0.5): (6.01621994111549, 25.7411909367237, 74.9360523040282),
+            ("lbf", 3.5, 0.75): (-4.96647097336035, -3.64053694937599, -26.9746205340027)}
+    rows = {(r["form"], r["r"], r["lam"]): r["values"] for r in CLOSED["pairs"]}
+    for key, v in want.items():
+        assert np.allclose(rows[key][:3], v, rtol=1e-13), key
+    # lambda = 1 is the plain potential (Beutler: lv = 1 gives x = (s/r)^6)
+    plain = O.pair_probe(3.5, 3.2, 0.12, -0.3, False, O.Params(9.0, 1.0, 0.2, 0.5, O.BEUTLER), 0.5)[0]
+    assert plain == pytest.approx(want[("beutler", 3.5, 1.0)][0], rel=1e-13)

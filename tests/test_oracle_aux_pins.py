@@ -164,9 +164,60 @@ def test_opes_generalized_force_sign_flip():
     assert a["f_theta"] == pytest.approx(-10.0) and b["f_theta"] == pytest.approx(10.0)
 
 
-def test_standard_weights_reweight_by_bias():
-    op = Op.DualOpes(KT)
-    op.deposit(0.5)
-    u_before = op.bias(0.52)[0]
-    op.deposit(0.52)
-    assert op.w_std[1] == pytest.approx(math.exp(u_before / KT), rel=1e-13)
+def test_opes_rho_bar_is_the_mean_over_three_centres():
+    """Explore kernels (equal weights) at 0.2, 0.3 and 1.0 with sigma = 0.05:
+    the close pair overlaps by exp(-2), the far one is isolated (every other
+    overlap, images included, is below exp(-100)).  Worked by hand:
+    rho_hat(0.2) = rho_hat(0.3) = (1 + e^-2)/3, rho_hat(1.0) = 1/3, so the
+    mean over the centres is (3 + 2 e^-2)/9 (a median or maximum would give
+    (1 + e^-2)/3) and at theta = 1 the ratio is 3/(3 + 2 e^-2) (eq. 11)."""
+    op = Op.DualOpes(KT, sigma=0.05)
+    for th in (0.2, 0.3, 1.0):
+        op.centers.append(th)
+        op.w_std.append(1.0)
+    g, nu, eps = op.c_expl
+    e2 = math.exp(-2.0)
+    want_ratio = 3.0 / (3.0 + 2.0 * e2)
+    u, _ = op._bias_one(1.0, [1.0, 1.0, 1.0], op.c_expl)
+    assert u == pytest.approx(nu * KT * math.log(want_ratio + eps), rel=1e-13)
+    u2, _ = op._bias_one(0.2, [1.0, 1.0, 1.0], op.c_expl)
+    assert u2 == pytest.approx(nu * KT * math.log(3.0 * (1.0 + e2) / (3.0 + 2.0 * e2) + eps), rel=1e-13)
+
+
+def test_standard_weights_recover_the_unbiased_density():
+    """OPES-Standard reweights its kernels so that rho_hat converges to the
+    unbiased distribution (text after eq. 13).  Samples drawn from a known
+    biased density p(theta) ~ p*(theta) exp(-V(theta)/kT), deposited with
+    the bias V in place, must give rho_hat = (p* convolved with the kernel)
+    within sampling error; with p* ~ 1 + cos(pi theta)/2 on [0, 2) that
+    smoothed target is sigma sqrt(2 pi) (1 + e^(-pi^2 sigma^2/2) cos(pi theta)/2)/2.
+    Weights exp(-V/kT) or equal weights miss it by factors of e^(+-3) and
+    e^(+-1.5)."""
+    rng = np.random.default_rng(2608)
+    sigma = 0.1
+    amp = 1.5 * KT
+    V = lambda t: amp * math.sin(math.pi * t)
+    # rejection sampling from p* exp(-V/kT) on [0, 2)
+    n, xs = 20000, []
+    bound = 1.5 * math.exp(amp / KT)
+    while len(xs) < n:
+        t = rng.uniform(0.0, 2.0, 4 * n)
+        y = rng.uniform(0.0, bound, 4 * n)
+        keep = y < (1.0 + 0.5 * np.cos(np.pi * t)) * np.exp(-amp * np.sin(np.pi * t) / KT)
+        xs.extend(t[keep].tolist())
+    xs = xs[:n]
+    op = Op.DualOpes(KT, sigma=sigma)
+    op.bias = lambda th: (V(th), 0.0)   # the bias in force when each sample was taken
+    for th in xs:
+        op.deposit(th)
+    w = np.asarray(op.w_std)
+    assert np.allclose(w, np.exp(np.array([V(t) for t in xs]) / KT), rtol=1e-12)
+    c = np.asarray(op.centers)
+    for th in (0.1, 0.5, 0.9, 1.3, 1.7):
+        d = th - c
+        g = sum(np.exp(-0.5 * (d + img) ** 2 / sigma ** 2) for img in (-2.0, 0.0, 2.0))
+        rho = float((w * g).sum() / w.sum())
+        want = sigma * math.sqrt(2 * math.pi) * (1 + math.exp(-(math.pi * sigma) ** 2 / 2) *
+                                                 math.cos(math.pi * th) / 2) / 2
+        assert rho == pytest.approx(want, rel=0.08), th
+        assert Op.DualOpes._rho(op, th, op.w_std)[0] == pytest.approx(rho, rel=1e-10)
