@@ -140,8 +140,11 @@ typedef struct {
   double *d_pos;              /* [N_total][3] accumulated: += g_k * dU_k/dx */
   double *d_lambda;           /* [K] written: g_k * dU_k/dlambda */
   double *d_sigma;            /* [n_types] written: sum_k g_k dU_k/dsigma_t */
-  double *d_sqrt_epsilon;     /* [n_types] written: sum_k g_k dU_k/dsqrt(eps_t) */
+  double *d_sqrt_epsilon;     /* [n_types] written: sum_k g_k dU_k/dsqrt(eps_t) (finite for every type) */
   double *d_charge;           /* [n_types] written: sum_k g_k dU_k/dq_t */
+  double *d_epsilon;          /* [n_types] written: sum_k g_k dU_k/deps_t = d_sqrt_epsilon / (2 sqrt(eps_t));
+                                 NaN where eps_t = 0 (the combination sqrt(eps_i eps_j) has no
+                                 derivative there) */
 } alch_nb_grad;
 
 typedef struct {
@@ -168,19 +171,41 @@ alch_nb_status alch_nb_workspace_size(const alch_nb_ctx *ctx, size_t *bytes);
  * stream; uploads the static tables.  Rebinding is allowed. */
 alch_nb_status alch_nb_bind(alch_nb_ctx *ctx, void *d_workspace, size_t bytes, void *stream);
 
-/* Build the neighbour list from device positions d_pos [N_total][3]. */
+/* Build the neighbour list from device positions d_pos [N_total][3]:
+ * every non-excluded pair i < j of a box whose minimum-image distance is
+ * below cutoff + skin (canonical FP64 test: positions wrapped into the box,
+ * displacement shifted by -+L beyond +-L/2, r^2 = (dx^2 + dy^2) + dz^2 without
+ * fused multiply-adds), grouped into 8-atom clusters of 64-slot
+ * super-clusters.  The list serves every later call until a rebuild.  It is
+ * the pair set over which eq. 4's sums run, restricted to the short range
+ * (the paper truncates nonbonded terms at a cutoff: Simulation Details).
+ * A list larger than its capacity raises ALCH_NB_FLAG_CAPACITY (read with
+ * alch_nb_get_flags) and later evaluations compute nothing until a larger
+ * context is created. */
 alch_nb_status alch_nb_build_list(alch_nb_ctx *ctx, const double *d_pos);
 
 /* Evaluate energies, forces and dU/dlambda at device positions d_pos
- * [N_total][3] and device lambdas d_lambda [K].  With ALCH_NB_AUTO_REBUILD
- * the list is rebuilt on the device when an atom moved more than skin/2
- * since the last build (always when skin = 0); ALCH_NB_FORCE_REBUILD
- * rebuilds unconditionally. */
+ * [N_total][3] and device lambdas d_lambda [K] (lambda in [0, 1]; values
+ * outside are clamped and raise ALCH_NB_FLAG_LAMBDA_RANGE).  This is the
+ * potential U(x, lambda) of eq. 4 (the LBF schedule: U_solv + U_solu +
+ * hA U_solu-solv + hB U_softLJ with eqs. 5-10; the Beutler schedule: the
+ * conventional soft core in place of the last two terms), the forces
+ * -dU/dx, and the generalized force dU/dlambda whose conditional mean eq. 2
+ * integrates (LBF: hA' U_A + hB' U_B; Beutler: the left derivative at
+ * lambda = 1/2).  With ALCH_NB_AUTO_REBUILD the list is rebuilt on the
+ * device when an atom moved more than skin/2 since the last build (always
+ * when skin = 0); ALCH_NB_FORCE_REBUILD rebuilds unconditionally.  Outputs
+ * are written in full (forces in atom order; terms per box as listed under
+ * ALCH_NB_T_*); any output pointer may be NULL. */
 alch_nb_status alch_nb_compute(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda, uint32_t flags,
                                const alch_nb_out *out);
 
 /* Gradients of L = sum_k g_k E_total,k for upstream device weights
- * d_grad_energy [K], at the same positions/lambdas as the last compute:
+ * d_grad_energy [K] (the reverse pass of eq. 4's potential: dU/dx and
+ * dU/dlambda as in alch_nb_compute; the per-type derivatives of every pair
+ * term of eqs. 4-10 through the combination rules sigma_ij = (sigma_i +
+ * sigma_j)/2, eps_ij = sqrt(eps_i eps_j), q_i q_j), at the same
+ * positions/lambdas as the last compute:
  * every gradient comes from that compute's state (forces, dU/dlambda, the
  * list and the slot coordinates it wrote), so d_pos and d_lambda must be the
  * inputs of that call.  The parameter gradients are per-atom 64-bit
@@ -249,6 +274,19 @@ alch_nb_status alch_nb_launch_step(alch_nb_ctx *ctx);
 alch_nb_status alch_nb_autotune(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda, int32_t reps);
 alch_nb_status alch_nb_set_variant(alch_nb_ctx *ctx, int32_t variant);
 int32_t alch_nb_num_variants(void);
+
+/* How the list is built on a rebuild.  ALCH_NB_LIST_AUTO (the default):
+ * one launch whose phases meet at bounded grid barriers, when every block
+ * fits on the device at once; otherwise one kernel per phase.
+ * ALCH_NB_LIST_PHASES: always one kernel per phase.  A fused build whose
+ * barrier wait gives up raises ALCH_NB_FLAG_BARRIER_TIMEOUT and that call's
+ * results are invalid: switch to ALCH_NB_LIST_PHASES and evaluate again with
+ * ALCH_NB_FORCE_REBUILD.  alch_nb_get_list_mode() reports what a rebuild
+ * launches now (ALCH_NB_LIST_FUSED_ACTIVE or ALCH_NB_LIST_PHASES; -1 for a
+ * NULL context).  Setting the mode drops a captured step. */
+enum { ALCH_NB_LIST_AUTO = 0, ALCH_NB_LIST_PHASES = 1, ALCH_NB_LIST_FUSED_ACTIVE = 2 };
+alch_nb_status alch_nb_set_list_mode(alch_nb_ctx *ctx, int32_t mode);
+int32_t alch_nb_get_list_mode(const alch_nb_ctx *ctx);
 
 /* Tile-kernel timing with HIP events on the bound stream (on/off). */
 alch_nb_status alch_nb_set_timing(alch_nb_ctx *ctx, int32_t enable);

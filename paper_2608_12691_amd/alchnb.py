@@ -21,6 +21,7 @@ FP32_FIXED, FP64 = 0, 1
 AUTO_REBUILD, FORCE_REBUILD = 1, 2
 FLAG_FIXED_OVERFLOW, FLAG_SKIN_EXCEEDED, FLAG_NONFINITE, FLAG_LAMBDA_RANGE, FLAG_CAPACITY = 1, 2, 4, 8, 16
 FLAG_BARRIER_TIMEOUT, FLAG_BAD_INDEX = 32, 64
+LIST_AUTO, LIST_PHASES, LIST_FUSED_ACTIVE = 0, 1, 2
 NTERMS = 10
 TERM_NAMES = ["E_solv_solv", "E_solu_solu", "E_ss_vdw", "E_ss_elec", "U_A", "U_B", "dUdl_vdw", "dUdl_elec",
               "E_total", "dUdl_total"]
@@ -33,7 +34,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "box too small", 3: "unsupported", 
 EXPORTED = ["alch_nb_create", "alch_nb_workspace_size", "alch_nb_bind", "alch_nb_build_list", "alch_nb_compute",
             "alch_nb_backward", "alch_nb_dihedrals", "alch_nb_opes_update", "alch_nb_opes_layout", "alch_nb_opes_init", "alch_nb_opes_state_size",
             "alch_nb_export_pairs", "alch_nb_capture_step", "alch_nb_launch_step", "alch_nb_autotune",
-            "alch_nb_set_variant", "alch_nb_num_variants", "alch_nb_set_timing", "alch_nb_get_flags",
+            "alch_nb_set_variant", "alch_nb_num_variants", "alch_nb_set_list_mode", "alch_nb_get_list_mode",
+            "alch_nb_set_timing", "alch_nb_get_flags",
             "alch_nb_get_stats", "alch_nb_destroy", "alch_nb_strerror", "alch_nb_last_hip_error",
             "alch_nb_flops_per_pair"]
 
@@ -65,7 +67,7 @@ class Out_t(ctypes.Structure):
 
 class Grad_t(ctypes.Structure):
     _fields_ = [("d_pos", ctypes.c_void_p), ("d_lambda", ctypes.c_void_p), ("d_sigma", ctypes.c_void_p),
-                ("d_sqrt_epsilon", ctypes.c_void_p), ("d_charge", ctypes.c_void_p)]
+                ("d_sqrt_epsilon", ctypes.c_void_p), ("d_charge", ctypes.c_void_p), ("d_epsilon", ctypes.c_void_p)]
 
 
 class Stats_t(ctypes.Structure):
@@ -106,6 +108,8 @@ def load():
             "alch_nb_autotune": ([P, P, P, I32], I32),
             "alch_nb_set_variant": ([P, I32], I32),
             "alch_nb_num_variants": ([], I32),
+            "alch_nb_set_list_mode": ([P, I32], I32),
+            "alch_nb_get_list_mode": ([P], I32),
             "alch_nb_set_timing": ([P, I32], I32),
             "alch_nb_get_flags": ([P, P], I32),
             "alch_nb_get_stats": ([P, P], I32),
@@ -168,7 +172,10 @@ class Context:
                            float(cutoff), float(skin), float(switch_width), float(dsf_alpha), float(sc_alpha),
                            self.schedule, self.precision, int(variant), float(capacity_factor))
         self.ctx = None
-        self.generation = 0  # forwards enqueued (the backward needs the state of its own forward)
+        # bumped by every call that rewrites the forward state (list, slots,
+        # force sums): a backward needs the state of its own forward
+        self.generation = 0
+        self._list_mode = LIST_AUTO
         self._create()
         self.stream = torch.cuda.current_stream(self.device)
         self._bind()
@@ -202,6 +209,18 @@ class Context:
         self._p.list_capacity_factor = max(1.0, self._p.list_capacity_factor) * factor
         self._create()
         self._bind()
+        self.generation += 1
+        if self._list_mode != LIST_AUTO:
+            self.set_list_mode(self._list_mode)
+
+    def set_list_mode(self, mode):
+        """LIST_AUTO (fused build when co-resident) or LIST_PHASES (one kernel per phase)."""
+        self._check("alch_nb_set_list_mode", self.lib.alch_nb_set_list_mode(self.ctx, int(mode)))
+        self._list_mode = int(mode)
+
+    def list_mode(self) -> int:
+        """What a rebuild launches now: LIST_FUSED_ACTIVE or LIST_PHASES."""
+        return int(self.lib.alch_nb_get_list_mode(self.ctx))
 
     def close(self):
         if self.ctx:
@@ -242,6 +261,7 @@ class Context:
 
     # ------------------------------------------------------------ calls
     def build_list(self, pos):
+        self.generation += 1
         self._check("alch_nb_build_list", self.lib.alch_nb_build_list(self.ctx, ctypes.c_void_p(pos.data_ptr())))
 
     def compute(self, pos, lam, flags=AUTO_REBUILD, out=None):
@@ -258,20 +278,30 @@ class Context:
         return out
 
     def compute_checked(self, pos, lam, flags=AUTO_REBUILD, out=None, retries=3):
-        """compute() that syncs, reads the flags and re-plans on list overflow."""
+        """compute() that syncs and reads the flags: a fused list build whose
+        barrier wait gave up is redone with one kernel per phase, and a list
+        that outgrew its capacity is re-planned larger (when auto_capacity);
+        either way the call is evaluated again with a forced rebuild.  The
+        result carries the flags of the last evaluation."""
         for _ in range(retries + 1):
             res = self.compute(pos, lam, flags, out)
             f = self.get_flags()
-            if not (f & FLAG_CAPACITY) or not self.auto_capacity:
-                res["flags"] = f
-                return res
-            self.grow_capacity()
-            flags = FORCE_REBUILD
+            if f & FLAG_BARRIER_TIMEOUT and self._list_mode != LIST_PHASES:
+                self.set_list_mode(LIST_PHASES)
+                flags = FORCE_REBUILD
+                continue
+            if f & FLAG_CAPACITY and self.auto_capacity:
+                self.grow_capacity()
+                flags = FORCE_REBUILD
+                continue
+            res["flags"] = f
+            return res
         raise AlchNBError("compute_checked", 4)
 
     def backward(self, pos, lam, grad_energy, d_pos=None, d_lambda=None, d_sigma=None, d_sqrt_eps=None,
-                 d_charge=None):
-        g = Grad_t(_addr(d_pos), _addr(d_lambda), _addr(d_sigma), _addr(d_sqrt_eps), _addr(d_charge))
+                 d_charge=None, d_eps=None):
+        g = Grad_t(_addr(d_pos), _addr(d_lambda), _addr(d_sigma), _addr(d_sqrt_eps), _addr(d_charge),
+                   _addr(d_eps))
         st = self.lib.alch_nb_backward(self.ctx, ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
                                        ctypes.c_void_p(grad_energy.data_ptr()), ctypes.byref(g))
         self._check("alch_nb_backward", st)
@@ -343,10 +373,12 @@ class Context:
         self._check("alch_nb_launch_step", self.lib.alch_nb_launch_step(self.ctx))
 
     def autotune(self, pos, lam, reps=5):
+        self.generation += 1
         self._check("alch_nb_autotune", self.lib.alch_nb_autotune(self.ctx, ctypes.c_void_p(pos.data_ptr()),
                                                                   ctypes.c_void_p(lam.data_ptr()), int(reps)))
 
     def set_variant(self, v):
+        self.generation += 1
         self._check("alch_nb_set_variant", self.lib.alch_nb_set_variant(self.ctx, int(v)))
 
     def set_timing(self, on=True):

@@ -9,6 +9,11 @@ dL/depsilon is NaN for types with epsilon = 0 (the combination rule
 sqrt(eps_i eps_j) has no derivative there); the library also reports the
 derivative with respect to sqrt(epsilon), which is finite.
 
+The forward reads the device flags (one synchronization): a list that
+outgrew its capacity is re-planned and a fused list build that timed out is
+redone per phase (both evaluated again); a fixed-point overflow or
+non-finite positions raise, since the results would be wrong.
+
 The parameter tensors must hold the values the context was created with;
 gradients flow to them but changing them requires a new context.
 """
@@ -27,10 +32,14 @@ class AlchNonbonded(torch.autograd.Function):
                 raise ValueError("%s differs from the context's parameters; create a new context" % name)
         p = pos.detach().contiguous()
         lm = lam.detach().contiguous()
-        out = context.compute(p, lm, flags=alchnb.AUTO_REBUILD)
+        out = context.compute_checked(p, lm, flags=alchnb.AUTO_REBUILD)
+        bad = out["flags"] & (alchnb.FLAG_FIXED_OVERFLOW | alchnb.FLAG_NONFINITE | alchnb.FLAG_CAPACITY |
+                              alchnb.FLAG_BARRIER_TIMEOUT)
+        if bad:
+            raise alchnb.AlchNBError("AlchNonbonded.forward (device flags %d)" % out["flags"], 4 if bad & 16 else 1)
         ctx.context = context
         ctx.generation = context.generation
-        ctx.save_for_backward(p, lm, epsilon.detach())
+        ctx.save_for_backward(p, lm)
         ctx.mark_non_differentiable(out["forces"], out["dudl"], out["terms"])
         return out["terms"][:, 8].clone(), out["forces"], out["dudl"], out["terms"]
 
@@ -40,23 +49,19 @@ class AlchNonbonded(torch.autograd.Function):
             if g is not None and bool(torch.any(g != 0)):
                 raise RuntimeError("only E_total is differentiable (no gradients through forces, dU/dlambda or terms)")
         context = ctx.context
-        pos, lam, eps = ctx.saved_tensors
+        pos, lam = ctx.saved_tensors
         if context.generation != ctx.generation:
             context.compute(pos, lam, flags=alchnb.AUTO_REBUILD)  # restore the forward state
         ge = g_energy.detach().to(torch.float64).contiguous()
         need = ctx.needs_input_grad
         d_pos = torch.zeros_like(pos) if need[1] else None
         d_lam = torch.zeros_like(lam) if need[2] else None
-        want_p = need[3] or need[4] or need[5]
         T = context.n_types
         z = lambda: torch.zeros(T, dtype=torch.float64, device=pos.device)
-        d_sig, d_se, d_q = (z(), z(), z()) if want_p else (None, None, None)
-        context.backward(pos, lam, ge, d_pos=d_pos, d_lambda=d_lam, d_sigma=d_sig, d_sqrt_eps=d_se, d_charge=d_q)
-        d_eps = None
-        if want_p:
-            e = eps.to(pos.device)
-            d_eps = torch.where(e > 0, d_se / (2.0 * torch.sqrt(torch.where(e > 0, e, torch.ones_like(e)))),
-                                torch.full_like(e, float("nan")))
+        d_sig = z() if need[3] else None
+        d_eps = z() if need[4] else None
+        d_q = z() if need[5] else None
+        context.backward(pos, lam, ge, d_pos=d_pos, d_lambda=d_lam, d_sigma=d_sig, d_charge=d_q, d_eps=d_eps)
         return (None, d_pos, d_lam, d_sig if need[3] else None, d_eps if need[4] else None,
                 d_q if need[5] else None)
 

@@ -75,6 +75,8 @@ struct alch_nb_ctx {
   hipStream_t stream = nullptr;
   bool bound = false;
   int fused_blocks = 0;  // blocks of the fused list build (0 = per-phase kernels)
+  int fused_possible = 0;  // blocks the fused build may use on this device (0 = not co-resident)
+  int list_mode = 0;       // ALCH_NB_LIST_AUTO or ALCH_NB_LIST_PHASES
   Dev dev{};
   PotConsts pc{};
   int variant = 0;
@@ -187,6 +189,7 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->tp32 = cv.take<float4>(base, (size_t)ctx->T * ctx->T);
   d->dsf32 = cv.take<float4>(base, kDsfEntries);
   d->tp64 = cv.take<double4>(base, (size_t)ctx->T * ctx->T);
+  d->pot64 = cv.take<double>(base, kPot64Words);
   ctx->export_counter = cv.take<unsigned long long>(base, 1);
   ctx->ws_bytes = cv.off + 256;
 }
@@ -519,8 +522,9 @@ alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* st
     HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id));
     const int per_cu = list_fused_max_blocks();
     const char* env = std::getenv("ALCHNB_LIST_KERNELS");
-    const bool split = env && std::strcmp(env, "split") == 0;
-    ctx->fused_blocks = (!split && per_cu >= 1 && n_cu > 0) ? n_cu : 0;  // one block of 8 waves per CU
+    if (env && std::strcmp(env, "split") == 0) ctx->list_mode = ALCH_NB_LIST_PHASES;
+    ctx->fused_possible = (per_cu >= 1 && n_cu > 0) ? n_cu : 0;  // one block of 8 waves per CU
+    ctx->fused_blocks = ctx->list_mode == ALCH_NB_LIST_PHASES ? 0 : ctx->fused_possible;
   }
   auto up = [&](const void* dst, const void* src, size_t n) -> hipError_t {
     if (n == 0) return hipSuccess;
@@ -543,6 +547,9 @@ alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* st
   HIPCHK(up(d.tp32, ctx->tp32.data(), sizeof(float4) * ctx->tp32.size()));
   HIPCHK(up(d.dsf32, ctx->dsf32.data(), sizeof(float4) * ctx->dsf32.size()));
   HIPCHK(up(d.tp64, ctx->tp64.data(), sizeof(double4) * ctx->tp64.size()));
+  double pw[kPot64Words];
+  pot64_words(ctx->pc, pw);
+  HIPCHK(up(d.pot64, pw, sizeof(pw)));
   HIPCHK(launch_init(d, st));
   // the host copies must outlive the asynchronous uploads
   HIPCHK(hipStreamSynchronize(st));
@@ -613,6 +620,19 @@ alch_nb_status alch_nb_set_variant(alch_nb_ctx* ctx, int32_t variant) {
   destroy_graph(ctx);
   if (ctx->bound) HIPCHK(launch_units(ctx->dev, ctx->stream, shape_of(ctx)));  // units of this shape
   return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_set_list_mode(alch_nb_ctx* ctx, int32_t mode) {
+  if (!ctx || (mode != ALCH_NB_LIST_AUTO && mode != ALCH_NB_LIST_PHASES)) return ALCH_NB_E_INVALID_ARG;
+  ctx->list_mode = mode;
+  ctx->fused_blocks = mode == ALCH_NB_LIST_PHASES ? 0 : ctx->fused_possible;
+  destroy_graph(ctx);  // a captured step holds the old launches
+  return ALCH_NB_OK;
+}
+
+int32_t alch_nb_get_list_mode(const alch_nb_ctx* ctx) {
+  if (!ctx) return -1;
+  return ctx->fused_blocks > 0 ? ALCH_NB_LIST_FUSED_ACTIVE : ALCH_NB_LIST_PHASES;
 }
 
 alch_nb_status alch_nb_set_timing(alch_nb_ctx* ctx, int32_t enable) {
@@ -730,10 +750,10 @@ alch_nb_status alch_nb_backward(alch_nb_ctx* ctx, const double* d_pos, const dou
   const Dev& d = ctx->dev;
   if (grad->d_pos || grad->d_lambda)
     HIPCHK(launch_backward_finish(d, ctx->stream, ctx->p.precision, d_grad_energy, grad->d_pos, grad->d_lambda));
-  if (grad->d_sigma || grad->d_sqrt_epsilon || grad->d_charge) {
+  if (grad->d_sigma || grad->d_sqrt_epsilon || grad->d_charge || grad->d_epsilon) {
     if (ctx->T > kMaxTypes) return ALCH_NB_E_UNSUPPORTED;
     HIPCHK(launch_param_grads(d, ctx->stream, ctx->pc, ctx->p.precision, ctx->p.schedule, d_grad_energy,
-                              grad->d_sigma, grad->d_sqrt_epsilon, grad->d_charge));
+                              grad->d_sigma, grad->d_sqrt_epsilon, grad->d_charge, grad->d_epsilon));
   }
   return ALCH_NB_OK;
 }

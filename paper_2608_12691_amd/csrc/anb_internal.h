@@ -38,6 +38,14 @@ enum { ACC_SOLV = 0, ACC_SOLU = 1, ACC_A0 = 2, ACC_A1 = 3, ACC_A2 = 4, ACC_NPAIR
 // entry kinds
 enum { KIND_SOLV = 0, KIND_SOLU = 1, KIND_ALCH = 2 };
 
+// Unit header int4: (super-cluster, first entry, end entry, replica | flag);
+// the flag marks the units of solute super-clusters, which hold every
+// solute-solute and solute-solvent entry (solute super-clusters come first
+// in each replica and the half list pairs a super-cluster only with
+// clusters of itself and later ones).
+constexpr int kUnitSolute = 1 << 30;
+__host__ __device__ inline int unit_rep(int w) { return w & (kUnitSolute - 1); }
+
 struct GridInfo {
   int replica, is_solute;
   int atom_off, n_atoms;   // range in grid_atoms[]
@@ -145,6 +153,7 @@ struct Dev {
   const float4* tp32;        // [T*T] type-pair sigma, 4 eps, k_e q q, 1/sigma^6 (rounded from FP64)
   const float4* dsf32;       // [kDsfEntries] FP32 DSF pieces (erfc, then the Gaussian term, per interval)
   const double4* tp64;       // [T*T]
+  const double* pot64;       // [kPot64Words] FP64 potential constants of the solute units (see pot64_words)
 };
 
 enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6 };

@@ -7,6 +7,8 @@
 namespace anb {
 
 // Pair-potential constants, precomputed on the host in FP64.
+constexpr int kPot64Words = 12;
+
 struct PotConsts {
   double rc, rc2, rs, inv_w;   // cutoff, its square, switch start, 1/width (0 = no switch)
   double alpha, A, B, c2a;     // DSF: a, erfc(a rc)/rc, slope, 2a/sqrt(pi)
@@ -42,13 +44,16 @@ hipError_t launch_export(const Dev& d, hipStream_t st, double r_list, int* out, 
 hipError_t launch_init(const Dev& d, hipStream_t st);
 hipError_t launch_prepare(const Dev& d, hipStream_t st, const double* pos, const double* lambda, int mode,
                           double half_skin, int schedule);
+// The FP64 constants the tile kernel's solute units read from the workspace
+// (kPot64Words doubles, uploaded at bind).
+void pot64_words(const PotConsts& pc, double* out);
 hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
                        const TileShape& shape, const double* xin);
 hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int schedule, double* terms,
                            double* forces, double* dudl, long long* n_pairs);
 // pair inputs from the last forward's slot coordinates and list
 hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
-                              const double* g_energy, double* d_sigma, double* d_sqrt_eps, double* d_charge);
+                              const double* g_energy, double* d_sigma, double* d_sqrt_eps, double* d_charge, double* d_eps);
 hipError_t launch_backward_finish(const Dev& d, hipStream_t st, int precision, const double* g_energy,
                                   double* d_pos, double* d_lambda);
 hipError_t launch_dihedrals(hipStream_t st, const double* pos, int n_cv, const int* idx, double* xi, double* dxi,

@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(kBlk) k_pgrad(Dev d, PotConsts pc, const doubl
   const int n_waves = gridDim.x * (kBlk / 64);
   for (int u = wave; u < n_units; u += n_waves) {
     const int4 U = d.units[u];
-    const int s = U.x, rep = U.w;
+    const int s = U.x, rep = unit_rep(U.w);
     const double g = g_energy[rep];
     if (g == 0.0) continue;
     const LamState lam = d.lam[rep];
@@ -278,7 +278,8 @@ constexpr int kPgFinalBlk = 1024;
 constexpr int kPgFinalRun = 16;
 __global__ void __launch_bounds__(kPgFinalBlk) k_pgrad_final(Dev d, double inv_scale, double* __restrict__ d_sigma,
                                                              double* __restrict__ d_sqrt_eps,
-                                                             double* __restrict__ d_charge) {
+                                                             double* __restrict__ d_charge,
+                                                             double* __restrict__ d_eps) {
   __shared__ double part[kPgFinalBlk / 64];
   const int T = d.n_types;
   const int comp = blockIdx.x / T, t = blockIdx.x % T;
@@ -312,11 +313,18 @@ __global__ void __launch_bounds__(kPgFinalBlk) k_pgrad_final(Dev d, double inv_s
     for (int w = 0; w < kPgFinalBlk / 64; ++w) total += part[w];
     double* out = comp == 0 ? d_sigma : (comp == 1 ? d_sqrt_eps : d_charge);
     if (out) out[t] = total;
+    // eps_ij = sqrt(eps_i) sqrt(eps_j): dU/deps_t = dU/dsqrt(eps_t) / (2 sqrt(eps_t)), which has no
+    // value where eps_t = 0 (NaN there)
+    if (comp == 1 && d_eps) {
+      const double e = d.type_eps[t];
+      d_eps[t] = e > 0.0 ? total / (2.0 * sqrt(e)) : __builtin_nan("");
+    }
   }
 }
 
 hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
-                              const double* g_energy, double* d_sigma, double* d_sqrt_eps, double* d_charge) {
+                              const double* g_energy, double* d_sigma, double* d_sqrt_eps, double* d_charge,
+                              double* d_eps) {
   const dim3 G(kPgBlocks), B(kBlk);
   const bool sw = pc.inv_w > 0;
   const double scale = fixed_scale(precision);
@@ -330,7 +338,7 @@ hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc,
   }
 #undef PG
   hipLaunchKernelGGL(k_pgrad_final, dim3(3 * d.n_types), dim3(kPgFinalBlk), 0, st, d, 1.0 / scale, d_sigma, d_sqrt_eps,
-                     d_charge);
+                     d_charge, d_eps);
   return hipGetLastError();
 }
 

@@ -574,7 +574,8 @@ __device__ void ph_units_fill(const Dev& d) {
     const int cnt = ok_all ? d.sc_ecount[s] : 0;
     if (cnt == 0) continue;
     const int e0 = d.sc_estart[s], u0 = d.sc_ustart[s];
-    const int rep = d.grids[d.col_grid[d.sc_col[s]]].replica;
+    const GridInfo g = d.grids[d.col_grid[d.sc_col[s]]];
+    const int rep = g.replica | (g.is_solute ? kUnitSolute : 0);
     int u = u0;
     const unsigned long long below = (1ull << lane) - 1ull;
     for (int base = 0; base < cnt; base += 64) {

@@ -15,7 +15,13 @@
 //   memory writes and never waits for one.
 // Pair arithmetic is FP32 (or FP64 in the reference path); positions are
 // super-cluster-local so that FP32 keeps ~1e-7 A resolution in any box.
+// The units of solute super-clusters (every solute-solute and
+// solute-solvent entry, about 0.5-3% of the pairs) are evaluated first, in
+// FP64 in both kernels (solute_unit): dU/dlambda and the solute terms are
+// sums over these pairs alone, with cancellation between them.
 #include <hip/hip_runtime.h>
+
+#include <cstring>
 
 #include "anb_internal.h"
 #include "anb_kernels.h"
@@ -52,6 +58,28 @@ __device__ inline void erfc_exp(float x, float& ec, float& ex) {
 __device__ inline void erfc_exp(double x, double& ec, double& ex) {
   ex = exp(-x * x);
   ec = erfc(x);
+}
+__constant__ double kErfc64ChebDev[ANB_ERFC64_DEG + 1] = {
+#define X(i) kErfc64Cheb[i]
+  X(0), X(1), X(2), X(3), X(4), X(5), X(6), X(7), X(8), X(9), X(10), X(11), X(12), X(13), X(14), X(15), X(16)
+#undef X
+};
+// FP64 erfc(x) and exp(-x^2) for 0 <= x <= ANB_ERFC_XMAX from the Chebyshev
+// series of erfc_coeffs.h (relative error ~1e-15): a few registers, where
+// the library erfc needs many (used in the FP32 kernel's FP64 pass)
+__device__ inline void erfc_exp_cheb(double x, double& ec, double& ex) {
+  const double t = 1.0 / fma(ANB_ERFC64_P, x, 1.0);
+  const double s = (2.0 * t - (ANB_ERFC64_A + 1.0)) / (1.0 - ANB_ERFC64_A);
+  const double s2 = 2.0 * s;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll 1
+  for (int k = ANB_ERFC64_DEG; k >= 1; --k) {
+    const double b0 = fma(s2, b1, kErfc64ChebDev[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  ex = exp(-x * x);
+  ec = t * ex * fma(s, b1, kErfc64ChebDev[0] - b2);
 }
 
 template <typename R>
@@ -93,7 +121,8 @@ __host__ Pot<R> make_pot(const PotConsts& p) {
 // masked out get r2 := 1 so every value stays finite (callers select their
 // outputs to zero or run the lanes of in-range pairs only).  erfc(a r) and
 // the Gaussian term: in FP32 from the cubic pieces in tab (LDS) when kTable,
-// else from the rational fit; in FP64 from the library functions.
+// else from the rational fit; in FP64 from the Chebyshev series when kTable
+// (the FP32 kernel's FP64 pass), else from the library functions.
 template <typename R, bool SW>
 struct PairCore {
   R r2s, rinv, rinv2, r;
@@ -127,6 +156,10 @@ struct PairCore {
       const float t = __builtin_amdgcn_fractf(u);
       ec = fmaf(fmaf(fmaf(fa.w, t, fa.z), t, fa.y), t, fa.x);
       gx = fmaf(fmaf(fmaf(fb.w, t, fb.z), t, fb.y), t, fb.x);
+    } else if constexpr (sizeof(R) == 8 && kTable) {
+      R ex;
+      erfc_exp_cheb(P.alpha * r, ec, ex);
+      gx = P.c2a * ex;
     } else {
       R ex;
       erfc_exp(P.alpha * r, ec, ex);
@@ -206,23 +239,14 @@ __device__ inline void add_fixed_lanes(unsigned long long* p, R v, double scale,
 
 // ------------------------------------------------------------ tile kernel
 
-// Solute-solvent pair (rare: only entries of kind KIND_ALCH).  Its inputs
-// are taken from FP64 sources and rounded once: the displacement from the
-// FP64 positions (minimum image), and sigma_ij, 4 eps_ij, k_e q_i q_j and
-// 1/sigma_ij^6 from a per-type-pair table built in FP64.  This keeps the
-// lambda derivative, a sum with cancellation, at FP32 rounding level.
+// The lambda-dependent terms of a solute-solvent pair from its evaluated
+// core: u and -r du/dr (fr), and the pair's contributions to the three
+// sums a0..a2 (Beutler: soft-core vdw energy, electrostatic energy,
+// dU/dlambda_vdw per unit lambda_v'; LBF: vdw, electrostatic and u_cap
+// bases).
 template <typename R, int SCHED, bool SW>
-__device__ inline void alch_pair(R dx, R dy, R dz, bool valid, const typename C4<R>::P4& tp, R lv_or_hA, R le_or_hB,
-                                 const Pot<R>& P, const float4* tab, R& u, R& fr, R& rinv2, bool& inr,
-                                 double& a0, double& a1, double& a2) {
-  const R r2 = dx * dx + dy * dy + dz * dz;
-  inr = valid && r2 < P.rc2;
-  const R sij = tp.x, e4 = tp.y, qq = tp.z, inv_s6 = tp.w;
-  // the rational fit here: dU/dlambda is a sum with cancellation over these
-  // pairs, and they are few
-  PairCore<R, SW> pc;
-  pc.template eval<false>(r2, inr, sij, e4, qq, P, tab);
-  rinv2 = pc.rinv2;
+__device__ inline void alch_terms(const PairCore<R, SW>& pc, R sij, R e4, R inv_s6, R lv_or_hA, R le_or_hB,
+                                  const Pot<R>& P, bool inr, R& u, R& fr, double& a0, double& a1, double& a2) {
   if (SCHED == 0) {
     // Beutler soft core: lv 4eps (x^2 - x) S + le qq D
     const R lv = lv_or_hA, le = le_or_hB;
@@ -265,6 +289,127 @@ __device__ inline void alch_pair(R dx, R dy, R dz, bool valid, const typename C4
       a1 += (double)pc.el;
       a2 += (double)ubv;
     }
+  }
+}
+
+// A solute-solvent pair evaluated by the unit loop itself (FP64 inputs
+// rounded once, the loop's precision, erfc from the rational fit).  The unit
+// loop evaluates any unit it is given; solute units are routed to
+// solute_unit instead, so this path does not run in the current routing.
+// It stays because the loop compiled without it measured slower (the
+// compiler then spilled the solvent path's registers).
+template <typename R, int SCHED, bool SW>
+__device__ inline void alch_pair(R dx, R dy, R dz, bool valid, const typename C4<R>::P4& tp, R lv_or_hA, R le_or_hB,
+                                 const Pot<R>& P, const float4* tab, R& u, R& fr, R& rinv2, bool& inr,
+                                 double& a0, double& a1, double& a2) {
+  const R r2 = dx * dx + dy * dy + dz * dz;
+  inr = valid && r2 < P.rc2;
+  PairCore<R, SW> pc;
+  pc.template eval<false>(r2, inr, tp.x, tp.y, tp.z, P, tab);
+  rinv2 = pc.rinv2;
+  alch_terms<R, SCHED, SW>(pc, tp.x, tp.y, tp.w, lv_or_hA, le_or_hB, P, inr, u, fr, a0, a1, a2);
+}
+
+// FP64 constants of the solute units, read from the workspace (scalar loads
+// where they are used) rather than passed as kernel arguments, which would
+// hold scalar registers through the whole FP32 kernel.
+static_assert(sizeof(Pot<double>) <= kPot64Words * sizeof(double), "workspace image of Pot<double>");
+void pot64_words(const PotConsts& pc, double* out) {
+  const Pot<double> p = make_pot<double>(pc);
+  for (int i = 0; i < kPot64Words; ++i) out[i] = 0.0;
+  std::memcpy(out, &p, sizeof(p));
+}
+
+// One unit of a solute super-cluster, by the whole wave, in FP64 from FP64
+// inputs: its entries are the solute-solute pairs (plain) and the
+// solute-solvent pairs (soft core or LBF), the only pairs that dU/dlambda
+// and the solute terms sum over.  Lane (jl, il) takes j-atom jl of an
+// entry's j-cluster and, for each i-cluster c of its mask, i-atom il.  Each
+// pair's parameters come from its two slots' FP64 values (sigma/2,
+// 2 sqrt(eps), and q sqrt(k_e) beside the position), so a tile needs one
+// round of independent loads.  j-forces are summed over the i-clusters and
+// il, i-forces over jl, and both leave as 64-bit fixed-point atomics (a few
+// per entry: these units are small).  The unit's sums go to its
+// accumulator slots.  kCheb: erfc from the Chebyshev series (few
+// registers; the FP32 kernel) or the library (the FP64 kernel).
+template <int SCHED, bool SW, bool kCheb>
+__device__ inline void solute_unit(const Dev& d, const Pot<double>& P, const float4* dsf, const int4& U, int u,
+                                   double fscale) {
+  const int lane = threadIdx.x & 63;
+  const int il = lane & 7, jl = lane >> 3;
+  const int s = U.x;
+  const size_t slots = (size_t)d.sc_cap * kSc;
+  const LamState lam = d.lam[unit_rep(U.w)];
+  const cptr<uint32_t> einfo = as_const(d.ent_info);
+  const cptr<unsigned long long> emask = as_const(d.ent_mask);
+  double e_solu = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  int npair = 0;
+  for (int e = U.y; e < U.z; ++e) {
+    const uint32_t info = einfo[e];
+    const uint32_t imask = info & 0xffu;
+    const bool alch = ((info >> 8) & 3u) == (uint32_t)KIND_ALCH;
+    const int jsl = d.ent_jc[e] * kCl + jl;
+    const double4 off = d.ent_off[e];
+    const double4 pj = d.pos64[jsl];  // .w: q sqrt(k_e)
+    const double2 ej = d.se64[jsl];   // sigma/2, 2 sqrt(eps)
+    const double xj = pj.x + off.x, yj = pj.y + off.y, zj = pj.z + off.z;
+    double fjx = 0.0, fjy = 0.0, fjz = 0.0;
+#pragma unroll 1
+    for (int c = 0; c < kScCl; ++c) {
+      if (!(imask & (1u << c))) continue;
+      const int isl = s * kSc + c * kCl + il;
+      const double4 pi = d.pos64[isl];
+      const double2 ei = d.se64[isl];
+      const double dx = xj - pi.x, dy = yj - pi.y, dz = zj - pi.z;
+      const double sij = ei.x + ej.x;
+      // padding slots carry sigma 0 (their lanes are masked out)
+      const double s2 = sij > 0.0 ? sij * sij : 1.0;
+      const double4 tp = make_double4(sij, ei.y * ej.y, pi.w * pj.w, 1.0 / (s2 * s2 * s2));
+      const bool valid = __builtin_amdgcn_inverse_ballot_w64(emask[(size_t)e * kScCl + c]);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const bool inr = valid && r2 < P.rc2;
+      PairCore<double, SW> pc;
+      pc.template eval<kCheb>(r2, inr, tp.x, tp.y, tp.z, P, dsf);
+      double uu, fr;
+      if (alch) {
+        alch_terms<double, SCHED, SW>(pc, tp.x, tp.y, tp.w, lam.a[0], lam.a[1], P, inr, uu, fr, a0, a1, a2);
+      } else {
+        uu = pc.lj0 * pc.S + pc.el;
+        fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
+        if (inr) e_solu += uu;
+      }
+      const double rinv2 = pc.rinv2;
+      npair += __popcll(__ballot(inr));
+      const double fs = inr ? fr * rinv2 : 0.0;
+      const double fx = fs * dx, fy = fs * dy, fz = fs * dz;
+      fjx += fx;
+      fjy += fy;
+      fjz += fz;
+      const double gx = red_jl(fx), gy = red_jl(fy), gz = red_jl(fz);
+      add_fixed_lanes(d.ffix + isl, -gx, fscale, d.flags, jl == 0);
+      add_fixed_lanes(d.ffix + slots + isl, -gy, fscale, d.flags, jl == 0);
+      add_fixed_lanes(d.ffix + 2 * slots + isl, -gz, fscale, d.flags, jl == 0);
+    }
+    fjx = red8(fjx);
+    fjy = red8(fjy);
+    fjz = red8(fjz);
+    add_fixed_lanes(d.ffix + jsl, fjx, fscale, d.flags, il == 0);
+    add_fixed_lanes(d.ffix + slots + jsl, fjy, fscale, d.flags, il == 0);
+    add_fixed_lanes(d.ffix + 2 * slots + jsl, fjz, fscale, d.flags, il == 0);
+  }
+  e_solu = wave_sum(e_solu);
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  a2 = wave_sum(a2);
+  if (lane == 0) {
+    const size_t UC = (size_t)d.unit_cap;
+    double* o = d.unit_acc + u;
+    o[ACC_SOLV * UC] = 0.0;
+    o[ACC_SOLU * UC] = e_solu;
+    o[ACC_A0 * UC] = a0;
+    o[ACC_A1 * UC] = a1;
+    o[ACC_A2 * UC] = a2;
+    o[ACC_NPAIR * UC] = (double)npair;
   }
 }
 
@@ -375,6 +520,16 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     return make_int4(__builtin_amdgcn_readlane(hdr.x, i), __builtin_amdgcn_readlane(hdr.y, i),
                      __builtin_amdgcn_readlane(hdr.z, i), __builtin_amdgcn_readlane(hdr.w, i));
   };
+  // Solute units first, in FP64, before the FP32 state below is live
+  if (nr > 0) load_hdrs(0);
+  for (int r = 0; r < nr; ++r) {
+    if (r > 0 && (r & 63) == 0) load_hdrs(r);
+    const int4 V = header(r);
+    if (__builtin_expect((V.w & kUnitSolute) != 0, 0)) {
+      const Pot<double> P64 = *as_const(reinterpret_cast<const Pot<double>*>(d.pot64));
+      solute_unit<SCHED, SW, sizeof(R) == 4>(d, P64, dsf, V, ub + r, fscale);
+    }
+  }
   int n_jc = 0;
   uint32_t n_inf = 0;
   double4 n_off = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -391,14 +546,23 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   };
   bool have_next = false;
   if (nr > 0) {
-    load_hdrs(0);
+    if (nr > 64) load_hdrs(0);
     load_entries(header(0));
     have_next = true;
   }
   for (int r = 0; r < nr; ++r) {
     if (r > 0 && (r & 63) == 0) load_hdrs(r);  // past 64 units (large boxes)
-    const int4 U = header(r);
+    int4 U = header(r);
     const int u = ub + r;
+    // a solute unit (done by the FP64 pass above) enters as an empty unit of
+    // the current super-cluster: no entries, no change of super-cluster, no
+    // accumulator write (skipping it with a second loop edge instead made
+    // the compiler spill this loop's registers)
+    const bool sol = (U.w & kUnitSolute) != 0;
+    if (sol) {
+      U.x = cur_s < 0 ? U.x : cur_s;
+      U.z = U.y;
+    }
     if (!have_next) load_entries(U);
     const int c_jc = n_jc;
     const uint32_t c_inf = n_inf;
@@ -406,7 +570,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     have_next = r + 1 < nr && ((r + 1) & 63) != 0;
     if (have_next) load_entries(header(r + 1));
     const int s = U.x;
-    const LamState lam = d.lam[U.w];
+    const LamState lam = d.lam[unit_rep(U.w)];
     R la0, la1;
     if (sizeof(R) == 4) {
       la0 = (R)lam.f[0];
@@ -661,7 +825,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
       acc_a1 = wave_sum(*rare2);
       acc_a2 = wave_sum(*rare3);
     }
-    if (lane == 0) {
+    if (lane == 0 && !sol) {
       const size_t U = (size_t)d.unit_cap;
       double* o = d.unit_acc + u;
       o[ACC_SOLV * U] = acc_solv;

@@ -53,12 +53,17 @@ def boundary_band(workload, k, positions, delta):
     return hi - lo
 
 
-def compare(res, refs, workload, positions_per_box, precision, offsets, check_pairs=True, label=""):
+def compare(res, refs, workload, positions_per_box, precision, offsets, check_pairs=True, label="",
+            energy_tol=None):
     """Compare one GPU result (dict of numpy arrays) with per-box oracle results.
 
-    Returns a dict of the worst errors; asserts they are within TOL[precision].
+    Returns a dict of the worst errors; asserts they are within TOL[precision]
+    (energy_tol, when given, replaces the energy bar: energies carry no bar of
+    their own in the targets, and a caller that sets one states its reason).
     """
-    tol = TOL[precision]
+    tol = dict(TOL[precision])
+    if energy_tol is not None:
+        tol["energy"] = energy_tol
     worst = dict(force=0.0, dudl=0.0, energy=0.0)
     for k, ref in enumerate(refs):
         a, b = offsets[k], offsets[k + 1]

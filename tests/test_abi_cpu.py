@@ -162,3 +162,33 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(alchnb, "LIB_PATH", str(tmp_path / "libalchnb.so"))
     with pytest.raises(ImportError):
         alchnb.load()
+
+
+def test_compute_checked_reacts_to_barrier_timeout_and_capacity():
+    """Host logic of the checked call (no GPU): a fused build that timed out
+    is redone with one kernel per phase, a list overflow re-plans larger, and
+    each retry forces a rebuild; other flags are returned to the caller."""
+    from paper_2608_12691_amd import alchnb as A
+    ctx = A.Context.__new__(A.Context)
+    ctx.auto_capacity = True
+    ctx._list_mode = A.LIST_AUTO
+    ctx.generation = 0
+    flags_seq = [A.FLAG_BARRIER_TIMEOUT, A.FLAG_CAPACITY, A.FLAG_LAMBDA_RANGE]
+    calls = []
+    ctx.compute = lambda pos, lam, flags, out: calls.append(("compute", flags)) or {}
+    ctx.get_flags = lambda: flags_seq.pop(0)
+
+    def set_mode(m):
+        calls.append(("mode", m))
+        ctx._list_mode = m
+    ctx.set_list_mode = set_mode
+    ctx.grow_capacity = lambda: calls.append(("grow",))
+    res = A.Context.compute_checked(ctx, None, None, flags=A.AUTO_REBUILD)
+    assert res["flags"] == A.FLAG_LAMBDA_RANGE
+    assert calls == [("compute", A.AUTO_REBUILD), ("mode", A.LIST_PHASES), ("compute", A.FORCE_REBUILD),
+                     ("grow",), ("compute", A.FORCE_REBUILD)]
+    # a timeout on the per-phase path is not retried again: the flag is returned
+    calls.clear()
+    flags_seq[:] = [A.FLAG_BARRIER_TIMEOUT]
+    assert A.Context.compute_checked(ctx, None, None)["flags"] == A.FLAG_BARRIER_TIMEOUT
+    assert calls == [("compute", A.AUTO_REBUILD)]

@@ -270,22 +270,126 @@ def test_autotune_keeps_parity_and_caches(tmp_path, monkeypatch):
         compare(r, [ref], w, [w.systems[0].positions], 0, _offsets(w), label="variant %d" % vv)
 
 
+_CFG4_REFS = {}
+
+
+def _cfg4_refs(w, schedule, positions=None, lams=None):
+    """Oracle results of every config-4 box (cached per schedule for the unperturbed boxes)."""
+    key = (schedule,) if positions is None else None
+    if key and key in _CFG4_REFS:
+        return _CFG4_REFS[key]
+    lams = w.lambdas if lams is None else lams
+    refs = [oracle_for(w, k, lams[k], schedule, positions=None if positions is None else positions[k])
+            for k in range(len(w.systems))]
+    if key:
+        _CFG4_REFS[key] = refs
+    return refs
+
+
+def _per_box(w, res, refs, positions, precision, label):
+    off = _offsets(w)
+    for k in range(len(w.systems)):
+        sub = {kk: (v[off[k]:off[k + 1]] if kk == "forces" else v[k:k + 1]) for kk, v in res.items() if kk != "flags"}
+        one = S.Workload(w.name, [w.systems[k]], w.ff, w.cutoff, w.skin, w.switch_width, w.dsf_alpha, w.sc_alpha,
+                         w.lambdas[k:k + 1], w.seed)
+        compare(sub, [refs[k]], one, [positions[k]], precision, np.array([0, off[k + 1] - off[k]]),
+                label="%s box %d" % (label, k))
+
+
 @pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
 @pytest.mark.parametrize("schedule", [O.BEUTLER, O.LBF], ids=["beutler", "lbf"])
 def test_config4_batched_replicas(precision, schedule):
-    """16 boxes of 2,000-12,000 atoms at lambda_k = k/15 in one launch; sampled boxes vs the oracle
+    """16 boxes of 2,000-12,000 atoms at lambda_k = k/15 in one launch; every box vs the oracle
     (each box with its own lambda factors, for both schedules)."""
     w = workload(4)
     ctx = _ctx(w, precision, schedule)
+    print("config4 precision=%d schedule=%d" % (precision, schedule), flush=True)
     res, pos = _run(ctx, w, w.lambdas, flags=2)
+    assert res["flags"] == 0
+    _per_box(w, res, _cfg4_refs(w, schedule), pos, precision, "cfg4")
+
+
+def test_config4_graph_replay_batched():
+    """The 16-box step captured as one hipGraph: every replay (new positions
+    and lambdas copied into the captured buffers, eager work and syncs in
+    between) is bit-identical to an eager call on the same inputs, and the
+    last replay matches the oracle in every box."""
+    w = workload(4)
+    xs0 = np.concatenate([s.positions for s in w.systems])
+    rng = np.random.Generator(np.random.PCG64(4040))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gctx = _ctx(w, 0)
+        gout = gctx.new_outputs()
+        gpos = gctx.positions(xs0)
+        glam = gctx.lambdas(w.lambdas)
+        gctx.compute_checked(gpos, glam, flags=2, out=gout)
+        gctx.capture_step(gpos, glam, gout)
+    ctx = _ctx(w, 0)
+    out = ctx.new_outputs()
+    pos = ctx.positions(xs0)
+    lam = ctx.lambdas(w.lambdas)
+    ctx.compute_checked(pos, lam, flags=2, out=out)
+    x = xs0.copy()
+    lams = np.array(w.lambdas, dtype=np.float64)
+    for t in range(1, 6):
+        print("graph replay %d" % t, flush=True)
+        x = x + rng.normal(0.0, 0.05, x.shape)
+        lams = np.clip(lams + rng.normal(0.0, 0.02, lams.shape), 0.0, 1.0)
+        xt = torch.as_tensor(x, device=pos.device)
+        lt = torch.as_tensor(lams, device=pos.device)
+        with torch.cuda.stream(stream):
+            gpos.copy_(xt)
+            glam.copy_(lt)
+            gctx.launch_step()
+        stream.synchronize()
+        pos.copy_(xt)
+        lam.copy_(lt)
+        ctx.compute(pos, lam, flags=1, out=out)
+        torch.cuda.synchronize()
+        a, b = to_numpy(gout), to_numpy(out)
+        for k in ("forces", "terms", "dudl", "n_pairs"):
+            assert np.array_equal(a[k], b[k]), (t, k)
+    assert gctx.get_flags() == 0 and ctx.get_flags() == 0
     off = _offsets(w)
-    for k in (0, 5, 10, 15):
-        sub = {kk: (v[off[k]:off[k + 1]] if kk == "forces" else v[k:k + 1]) for kk, v in res.items() if kk != "flags"}
-        ref = oracle_for(w, k, w.lambdas[k], schedule)
-        one = S.Workload(w.name, [w.systems[k]], w.ff, w.cutoff, w.skin, w.switch_width, w.dsf_alpha, w.sc_alpha,
-                         w.lambdas[k:k + 1], w.seed)
-        compare(sub, [ref], one, [w.systems[k].positions], precision, np.array([0, off[k + 1] - off[k]]),
-                label="cfg4 box %d" % k)
+    pos_k = [x[off[k]:off[k + 1]] for k in range(len(w.systems))]
+    wl = S.Workload(w.name, w.systems, w.ff, w.cutoff, w.skin, w.switch_width, w.dsf_alpha, w.sc_alpha, lams, w.seed)
+    refs = _cfg4_refs(wl, O.BEUTLER, positions=pos_k, lams=lams)
+    _per_box(wl, to_numpy(gout), refs, pos_k, 0, "cfg4 graph")
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_per_phase_list_build(k):
+    """The list built by one kernel per phase (the fallback of the fused
+    build) gives the oracle's pair set and parity, also after a walk with
+    device-side rebuilds."""
+    from paper_2608_12691_amd import alchnb
+    w = workload(k)
+    s = w.systems[0]
+    ctx = _ctx(w, 0)
+    ctx.set_list_mode(alchnb.LIST_PHASES)
+    assert ctx.list_mode() == alchnb.LIST_PHASES
+    pos = ctx.positions(w.systems)
+    ctx.build_list(pos)
+    assert np.array_equal(ctx.export_pairs(), O.pair_set(s.positions, s.exclusions, s.box, w.cutoff + w.skin))
+    res, p = _run(ctx, w, [0.6], flags=2)
+    assert res["flags"] == 0
+    compare(res, [oracle_for(w, 0, 0.6, O.BEUTLER)], w, p, 0, _offsets(w), label="phases cfg%d" % k)
+    if k == 2:
+        walk = S.perturbation_walk(s, 200, 0.02, seed=77)
+        lam = ctx.lambdas([0.3])
+        out = ctx.new_outputs()
+        n0 = ctx.get_stats()["n_rebuilds"]
+        for t in range(200):
+            ctx.compute(ctx.positions(walk[t]), lam, flags=1, out=out)
+        assert ctx.get_stats()["n_rebuilds"] > n0
+        assert ctx.get_flags() == 0
+        res = to_numpy(out)
+        compare(res, [oracle_for(w, 0, 0.3, O.BEUTLER, positions=walk[-1])], w, [walk[-1]], 0, _offsets(w),
+                label="phases walk")
+        ctx.build_list(ctx.positions(walk[-1]))
+        assert np.array_equal(ctx.export_pairs(), O.pair_set(walk[-1], s.exclusions, s.box, w.cutoff + w.skin))
+    ctx.set_list_mode(alchnb.LIST_AUTO)
 
 
 def _squeezed_waters(w, d_oo):
@@ -492,19 +596,12 @@ def test_box_at_the_size_limit_and_many_boxes(precision):
     res, p = _run(cm, wm, list(lams), flags=2)
     assert res["flags"] == 0
     refs = [oracle_for(wm, k, lams[k], O.BEUTLER) for k in range(40)]
-    if precision == 1:
-        compare(res, refs, wm, p, precision, _offsets(wm), label="many boxes")
-        return
-    # FP32: in boxes of 30-90 atoms with 3 solute atoms, dU/dlambda cancels down to 0.3-4% of
-    # sum |du/dlambda|, and the FP32 rounding of the pair terms (measured up to 4.5e-7 of that sum)
-    # is then above 1e-6 of |dU/dlambda|: here it is measured against sum |du/dlambda|.  Energy terms
-    # made of a few contact pairs carry their per-pair FP32 rounding (measured 1.0e-6 of sum |u|):
-    # checked at 1e-5 of sum |u| here
-    from parity import energy_error, force_error
-    off = _offsets(wm)
-    for k, ref in enumerate(refs):
-        assert force_error(res["forces"][off[k]:off[k + 1]], ref["forces"]) <= TOL[0]["force"], k
-        sc = ref["abs_terms"][9]
-        assert abs(res["dudl"][k] - ref["terms"][9]) <= TOL[0]["dudl"] * sc, k
-        assert max(energy_error(res["terms"][k, j], ref["terms"][j], ref["abs_terms"][j]) for j in range(10)) \
-            <= 10 * TOL[0]["energy"], k
+    # dU/dlambda cancels to 0.3-4% of sum |du/dlambda| in these boxes; the solute-solvent pairs are
+    # evaluated in FP64 in both kernels, so the relative bar holds in both precisions.  Energies: a
+    # box of 30-90 atoms has a few contact pairs at 2.6 A that dominate sum |u|; FP32 local
+    # coordinates (up to ~8 A from the super-cluster origin, half an ulp = 2.4e-7 A) give r^2 a
+    # relative error up to 2 x 2.4e-7 / 2.6 = 1.8e-7, which r^-12 = (r^2)^-6 multiplies by 6:
+    # ~1.1e-6 of such a pair's energy.  The FP32 energy bar here is that floor, 2e-6 (measured
+    # 1.0e-6); forces and dU/dlambda keep their bars
+    compare(res, refs, wm, p, precision, _offsets(wm), label="many boxes",
+            energy_tol=2e-6 if precision == 0 else None)
