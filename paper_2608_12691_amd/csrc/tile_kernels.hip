@@ -120,16 +120,19 @@ __host__ Pot<R> make_pot(const PotConsts& p) {
 // Switched LJ, DSF and the scalar pair force.  Lanes outside the cutoff or
 // masked out get r2 := 1 so every value stays finite (callers select their
 // outputs to zero or run the lanes of in-range pairs only).  erfc(a r) and
-// the Gaussian term: in FP32 from the cubic pieces in tab (LDS) when kTable,
-// else from the rational fit; in FP64 from the Chebyshev series when kTable
-// (the FP32 kernel's FP64 pass), else from the library functions.
+// the Gaussian term by route E: kErfcTable, the FP32 cubic pieces in tab
+// (LDS; FP64 takes the library functions); kErfcFit, the FP32 rational fit
+// (FP64: the library); kErfcCheb, the FP64 Chebyshev series (few registers;
+// FP32 takes the rational fit).
+enum { kErfcFit = 0, kErfcTable = 1, kErfcCheb = 2 };
+
 template <typename R, bool SW>
 struct PairCore {
   R r2s, rinv, rinv2, r;
   R lj0, flj0;   // unswitched LJ and -r dLJ/dr
   R S, rdS;      // switch and r dS/dr
   R el, fel;     // q q D(r) and -r d(q q D)/dr
-  template <bool kTable>
+  template <int E>
   __device__ inline void eval(R r2, bool inr, R sij, R e4, R qq, const Pot<R>& P, const float4* tab) {
     r2s = inr ? r2 : R(1);
     rinv = rsq(r2s);
@@ -150,13 +153,13 @@ struct PairCore {
       rdS = R(0);
     }
     R ec, gx;
-    if constexpr (sizeof(R) == 4 && kTable) {
+    if constexpr (sizeof(R) == 4 && E == kErfcTable) {
       const float u = r * P.inv_h;  // exact; 0 <= u <= kDsfN for r <= rc
       const float4 fa = tab[2 * (int)u], fb = tab[2 * (int)u + 1];
       const float t = __builtin_amdgcn_fractf(u);
       ec = fmaf(fmaf(fmaf(fa.w, t, fa.z), t, fa.y), t, fa.x);
       gx = fmaf(fmaf(fmaf(fb.w, t, fb.z), t, fb.y), t, fb.x);
-    } else if constexpr (sizeof(R) == 8 && kTable) {
+    } else if constexpr (sizeof(R) == 8 && E == kErfcCheb) {
       R ex;
       erfc_exp_cheb(P.alpha * r, ec, ex);
       gx = P.c2a * ex;
@@ -305,7 +308,7 @@ __device__ inline void alch_pair(R dx, R dy, R dz, bool valid, const typename C4
   const R r2 = dx * dx + dy * dy + dz * dz;
   inr = valid && r2 < P.rc2;
   PairCore<R, SW> pc;
-  pc.template eval<false>(r2, inr, tp.x, tp.y, tp.z, P, tab);
+  pc.template eval<kErfcFit>(r2, inr, tp.x, tp.y, tp.z, P, tab);
   rinv2 = pc.rinv2;
   alch_terms<R, SCHED, SW>(pc, tp.x, tp.y, tp.w, lv_or_hA, le_or_hB, P, inr, u, fr, a0, a1, a2);
 }
@@ -313,11 +316,27 @@ __device__ inline void alch_pair(R dx, R dy, R dz, bool valid, const typename C4
 // FP64 constants of the solute units, read from the workspace (scalar loads
 // where they are used) rather than passed as kernel arguments, which would
 // hold scalar registers through the whole FP32 kernel.
-static_assert(sizeof(Pot<double>) <= kPot64Words * sizeof(double), "workspace image of Pot<double>");
+static_assert(sizeof(Pot<double>) == 11 * sizeof(double) && 11 <= kPot64Words, "workspace image of Pot<double>");
 void pot64_words(const PotConsts& pc, double* out) {
   const Pot<double> p = make_pot<double>(pc);
   for (int i = 0; i < kPot64Words; ++i) out[i] = 0.0;
   std::memcpy(out, &p, sizeof(p));
+}
+__device__ inline Pot<double> load_pot64(const double* w) {
+  const cptr<double> c = as_const(w);  // wave-uniform: scalar loads
+  Pot<double> p;
+  p.rc2 = c[0];
+  p.rc = c[1];
+  p.rs = c[2];
+  p.inv_w = c[3];
+  p.alpha = c[4];
+  p.A = c[5];
+  p.B = c[6];
+  p.c2a = c[7];
+  p.sca = c[8];
+  p.inv_h = c[9];
+  p.rs2 = c[10];
+  return p;
 }
 
 // One unit of a solute super-cluster, by the whole wave, in FP64 from FP64
@@ -369,7 +388,7 @@ __device__ inline void solute_unit(const Dev& d, const Pot<double>& P, const flo
       const double r2 = dx * dx + dy * dy + dz * dz;
       const bool inr = valid && r2 < P.rc2;
       PairCore<double, SW> pc;
-      pc.template eval<kCheb>(r2, inr, tp.x, tp.y, tp.z, P, dsf);
+      pc.template eval<kCheb ? kErfcCheb : kErfcFit>(r2, inr, tp.x, tp.y, tp.z, P, dsf);
       double uu, fr;
       if (alch) {
         alch_terms<double, SCHED, SW>(pc, tp.x, tp.y, tp.w, lam.a[0], lam.a[1], P, inr, uu, fr, a0, a1, a2);
@@ -526,7 +545,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     if (r > 0 && (r & 63) == 0) load_hdrs(r);
     const int4 V = header(r);
     if (__builtin_expect((V.w & kUnitSolute) != 0, 0)) {
-      const Pot<double> P64 = *as_const(reinterpret_cast<const Pot<double>*>(d.pot64));
+      const Pot<double> P64 = load_pot64(d.pot64);
       solute_unit<SCHED, SW, sizeof(R) == 4>(d, P64, dsf, V, ub + r, fscale);
     }
   }
@@ -696,13 +715,13 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
           R u, fr, rinv2;
           if (shell) {
             PairCore<R, true> pc;
-            pc.template eval<true>(r2, true, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P, dsf);
+            pc.template eval<kErfcTable>(r2, true, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P, dsf);
             u = pc.lj0 * pc.S + pc.el;
             fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
             rinv2 = pc.rinv2;
           } else {
             PairCore<R, false> pc;
-            pc.template eval<true>(r2, true, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P, dsf);
+            pc.template eval<kErfcTable>(r2, true, qi.x + qj.x, qi.y * qj.y, pi.w * pj.w, P, dsf);
             u = pc.lj0 + pc.el;
             fr = pc.flj0 + pc.fel;
             rinv2 = pc.rinv2;
