@@ -63,7 +63,8 @@ enum {
   ALCH_NB_E_CAPACITY = 4,      /* the neighbour list outgrew its workspace */
   ALCH_NB_E_HIP = 5,           /* a HIP runtime call failed (see alch_nb_last_hip_error) */
   ALCH_NB_E_NOT_BOUND = 6,     /* the context has no workspace/stream yet */
-  ALCH_NB_E_NO_DEVICE = 7      /* no usable GPU */
+  ALCH_NB_E_NO_DEVICE = 7,     /* no usable GPU */
+  ALCH_NB_E_SCRATCH_SIZE = 8   /* the workspace exceeds the library's static device scratch */
 };
 
 enum { ALCH_NB_BEUTLER_DSF = 0, ALCH_NB_LBF_DSF = 1 };     /* schedule */
@@ -170,6 +171,23 @@ alch_nb_status alch_nb_workspace_size(const alch_nb_ctx *ctx, size_t *bytes);
 /* Bind a device workspace (>= workspace_size bytes, 256-byte aligned) and a
  * stream; uploads the static tables.  Rebinding is allowed. */
 alch_nb_status alch_nb_bind(alch_nb_ctx *ctx, void *d_workspace, size_t bytes, void *stream);
+
+/* Bind without allocating: for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Binds the context, on the current device, to a device array
+ * the library owns (ALCH_NB_STATIC_SCRATCH_BYTES on each GPU it runs on,
+ * held until the process ends) in place of a caller workspace, with the
+ * stream as in alch_nb_bind(); calls no allocating routine.  The context is
+ * then used as with alch_nb_bind().  Returns ALCH_NB_E_SCRATCH_SIZE when
+ * alch_nb_workspace_size() exceeds the array (nothing is bound then).
+ * One array per device serves one context at a time: binding takes it over
+ * from the previous owner, whose later calls return ALCH_NB_E_NOT_BOUND, and
+ * clears it.  Work of two contexts on one device that overlaps in time
+ * races on the array: the previous owner's enqueued work must have finished
+ * before another context is bound.  alch_nb_bind() or alch_nb_destroy()
+ * releases the array. */
+#define ALCH_NB_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+alch_nb_status alch_nb_bind_static(alch_nb_ctx *ctx, void *stream);
 
 /* Build the neighbour list from device positions d_pos [N_total][3]:
  * every non-excluded pair i < j of a box whose minimum-image distance is

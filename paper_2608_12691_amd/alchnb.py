@@ -29,9 +29,9 @@ OPES_GRID = 101
 OPES_HEADER = 16
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "box too small", 3: "unsupported", 4: "capacity", 5: "hip error",
-          6: "not bound", 7: "no device"}
+          6: "not bound", 7: "no device", 8: "workspace exceeds the static scratch"}
 
-EXPORTED = ["alch_nb_create", "alch_nb_workspace_size", "alch_nb_bind", "alch_nb_build_list", "alch_nb_compute",
+EXPORTED = ["alch_nb_create", "alch_nb_workspace_size", "alch_nb_bind", "alch_nb_bind_static", "alch_nb_build_list", "alch_nb_compute",
             "alch_nb_backward", "alch_nb_dihedrals", "alch_nb_opes_update", "alch_nb_opes_layout", "alch_nb_opes_init", "alch_nb_opes_state_size",
             "alch_nb_export_pairs", "alch_nb_capture_step", "alch_nb_launch_step", "alch_nb_autotune",
             "alch_nb_set_variant", "alch_nb_num_variants", "alch_nb_set_list_mode", "alch_nb_get_list_mode",
@@ -94,6 +94,7 @@ def load():
             "alch_nb_create": ([P, P, I32, P], I32),
             "alch_nb_workspace_size": ([P, P], I32),
             "alch_nb_bind": ([P, P, ctypes.c_size_t, P], I32),
+            "alch_nb_bind_static": ([P, P], I32),
             "alch_nb_build_list": ([P, P], I32),
             "alch_nb_compute": ([P, P, P, U32, P], I32),
             "alch_nb_backward": ([P, P, P, P, P], I32),
@@ -141,7 +142,7 @@ class Context:
 
     def __init__(self, ff, systems: Sequence, cutoff, skin, switch_width=1.0, dsf_alpha=0.2, sc_alpha=0.5,
                  schedule=BEUTLER_DSF, precision=FP32_FIXED, variant=-1, capacity_factor=1.0, device=None,
-                 auto_capacity=True):
+                 auto_capacity=True, static_scratch=False):
         import torch
         self.torch = torch
         self.lib = load()
@@ -176,6 +177,7 @@ class Context:
         # force sums): a backward needs the state of its own forward
         self.generation = 0
         self._list_mode = LIST_AUTO
+        self.static_scratch = bool(static_scratch)
         self._create()
         self.stream = torch.cuda.current_stream(self.device)
         self._bind()
@@ -197,6 +199,12 @@ class Context:
 
     def _bind(self):
         torch = self.torch
+        if self.static_scratch:
+            # the library's own device array: nothing is allocated here
+            self.ws = None
+            self._check("alch_nb_bind_static",
+                        self.lib.alch_nb_bind_static(self.ctx, ctypes.c_void_p(self.stream.cuda_stream)))
+            return
         self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
         aligned = (base + 255) & ~255

@@ -74,6 +74,7 @@ struct alch_nb_ctx {
   char* ws = nullptr;
   hipStream_t stream = nullptr;
   bool bound = false;
+  int static_dev = -1;   // device whose library-owned scratch holds the workspace (-1: caller's buffer)
   int fused_blocks = 0;  // blocks of the fused list build (0 = per-phase kernels)
   int fused_possible = 0;  // blocks the fused build may use on this device (0 = not co-resident)
   int list_mode = 0;       // ALCH_NB_LIST_AUTO or ALCH_NB_LIST_PHASES
@@ -103,6 +104,12 @@ static alch_nb_status hip_fail(alch_nb_ctx* c, hipError_t e) {
     hipError_t e_ = (call);                   \
     if (e_ != hipSuccess) return hip_fail(ctx, e_); \
   } while (0)
+
+// A context is usable when bound, and, if bound to the library-owned scratch
+// of a device, while no other context has been bound to that scratch since.
+static bool is_bound(const alch_nb_ctx* ctx) {
+  return ctx->bound && (ctx->static_dev < 0 || anb_static_owns(ctx, ctx->static_dev));
+}
 
 // ------------------------------------------------------------------ planning
 
@@ -214,6 +221,7 @@ const char* alch_nb_strerror(alch_nb_status s) {
     case ALCH_NB_E_HIP: return "HIP runtime error";
     case ALCH_NB_E_NOT_BOUND: return "context has no workspace bound";
     case ALCH_NB_E_NO_DEVICE: return "no usable GPU";
+    case ALCH_NB_E_SCRATCH_SIZE: return "workspace larger than the library's static device scratch";
     default: return "unknown status";
   }
 }
@@ -505,9 +513,22 @@ static void destroy_graph(alch_nb_ctx* ctx) {
 
 alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* stream) {
   if (!ctx || !d_ws) return ALCH_NB_E_INVALID_ARG;
+  if (ctx->static_dev >= 0) anb_static_release(ctx);
+  return anb_bind(ctx, d_ws, bytes, stream, -1);
+}
+
+}  // extern "C"
+
+// Bind to device memory: the caller's buffer (static_device < 0) or the
+// library-owned scratch of a device.  Clears the workspace, uploads the
+// static tables and waits for the uploads; allocates nothing.
+alch_nb_status anb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* stream, int static_device) {
+  if (!ctx || !d_ws) return ALCH_NB_E_INVALID_ARG;
   if (bytes < ctx->ws_bytes || (reinterpret_cast<uintptr_t>(d_ws) & 255u)) return ALCH_NB_E_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return ALCH_NB_E_NO_DEVICE;
+  ctx->bound = false;
+  ctx->static_dev = static_device;
   destroy_graph(ctx);
   ctx->ws = reinterpret_cast<char*>(d_ws);
   ctx->stream = reinterpret_cast<hipStream_t>(stream);
@@ -553,13 +574,12 @@ alch_nb_status alch_nb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* st
   HIPCHK(launch_init(d, st));
   // the host copies must outlive the asynchronous uploads
   HIPCHK(hipStreamSynchronize(st));
-  if (ctx->ev.empty()) {
-    ctx->ev.resize(2 * kTimingSlots);
-    for (auto& e : ctx->ev) HIPCHK(hipEventCreate(&e));
-  }
+  ctx->n_timed = 0;
   ctx->bound = true;
   return ALCH_NB_OK;
 }
+
+extern "C" {
 
 static TileShape shape_of(const alch_nb_ctx* ctx) {
   const Variant& v = kVariants[ctx->variant];
@@ -599,14 +619,14 @@ static alch_nb_status enqueue_compute(alch_nb_ctx* ctx, const double* pos, const
 alch_nb_status alch_nb_compute(alch_nb_ctx* ctx, const double* d_pos, const double* d_lambda, uint32_t flags,
                                const alch_nb_out* out) {
   if (!ctx) return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   if (!d_pos || !d_lambda) return ALCH_NB_E_INVALID_ARG;
   return enqueue_compute(ctx, d_pos, d_lambda, flags, out, true);
 }
 
 alch_nb_status alch_nb_build_list(alch_nb_ctx* ctx, const double* d_pos) {
   if (!ctx) return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   if (!d_pos) return ALCH_NB_E_INVALID_ARG;
   const Dev& d = ctx->dev;
   HIPCHK(launch_prepare(d, ctx->stream, d_pos, nullptr, 2, 0.5 * ctx->p.skin, ctx->p.schedule));
@@ -637,6 +657,11 @@ int32_t alch_nb_get_list_mode(const alch_nb_ctx* ctx) {
 
 alch_nb_status alch_nb_set_timing(alch_nb_ctx* ctx, int32_t enable) {
   if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (enable && ctx->ev.empty()) {
+    // created on first use, so that binding creates no HIP objects
+    ctx->ev.resize(2 * kTimingSlots);
+    for (auto& e : ctx->ev) HIPCHK(hipEventCreate(&e));
+  }
   ctx->timing = enable != 0;
   return ALCH_NB_OK;
 }
@@ -654,7 +679,7 @@ static alch_nb_status collect_timing(alch_nb_ctx* ctx) {
 
 alch_nb_status alch_nb_get_flags(alch_nb_ctx* ctx, uint32_t* flags) {
   if (!ctx || !flags) return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   unsigned int f = 0;
   HIPCHK(hipMemcpyAsync(&f, ctx->dev.flags, sizeof(f), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -693,7 +718,7 @@ alch_nb_status alch_nb_get_stats(alch_nb_ctx* ctx, alch_nb_stats* s) {
 
 alch_nb_status alch_nb_export_pairs(alch_nb_ctx* ctx, int32_t* d_pairs, int64_t cap, int64_t* n_out) {
   if (!ctx || !n_out || cap < 0 || (cap > 0 && !d_pairs)) return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   HIPCHK(hipMemsetAsync(ctx->export_counter, 0, sizeof(unsigned long long), ctx->stream));
   HIPCHK(launch_export(ctx->dev, ctx->stream, ctx->r_list, d_pairs, cap, ctx->export_counter));
   unsigned long long n = 0;
@@ -706,7 +731,7 @@ alch_nb_status alch_nb_export_pairs(alch_nb_ctx* ctx, int32_t* d_pairs, int64_t 
 alch_nb_status alch_nb_capture_step(alch_nb_ctx* ctx, const double* d_pos, const double* d_lambda,
                                     const alch_nb_out* out) {
   if (!ctx) return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   if (!d_pos || !d_lambda) return ALCH_NB_E_INVALID_ARG;
   if (!ctx->stream) return ALCH_NB_E_UNSUPPORTED;  // capture needs a non-null stream
   destroy_graph(ctx);
@@ -736,6 +761,7 @@ int32_t alch_nb_last_hip_error(const alch_nb_ctx* ctx) { return ctx ? (int32_t)c
 void alch_nb_destroy(alch_nb_ctx* ctx) {
   if (!ctx) return;
   if (ctx->bound && ctx->stream) hipStreamSynchronize(ctx->stream);
+  if (ctx->static_dev >= 0) anb_static_release(ctx);
   destroy_graph(ctx);
   for (auto& e : ctx->ev) hipEventDestroy(e);
   delete ctx;
@@ -744,7 +770,7 @@ void alch_nb_destroy(alch_nb_ctx* ctx) {
 alch_nb_status alch_nb_backward(alch_nb_ctx* ctx, const double* d_pos, const double* d_lambda,
                                 const double* d_grad_energy, const alch_nb_grad* grad) {
   if (!ctx) return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   if (!d_pos || !d_lambda || !d_grad_energy || !grad) return ALCH_NB_E_INVALID_ARG;
   (void)d_lambda;  // the lambda factors of the last forward are kept on the device
   const Dev& d = ctx->dev;
@@ -762,7 +788,7 @@ alch_nb_status alch_nb_dihedrals(alch_nb_ctx* ctx, const double* d_pos, int32_t 
                                  double* d_xi, double* d_dxi, const double* d_mass_inv, double* d_msum,
                                  const double* d_s, const double* d_kappa, double* d_u_dafed, double* d_forces) {
   if (!ctx) return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   if (n_cv < 0 || (n_cv > 0 && (!d_pos || !d_idx || !d_xi || !d_dxi))) return ALCH_NB_E_INVALID_ARG;
   if ((d_s == nullptr) != (d_kappa == nullptr)) return ALCH_NB_E_INVALID_ARG;
   if (n_cv == 0) return ALCH_NB_OK;
@@ -781,7 +807,7 @@ alch_nb_status alch_nb_opes_init(alch_nb_ctx* ctx, double* d_state, int32_t capa
   if (!ctx || !d_state || capacity < 1 || !(kT > 0) || !(sigma > 0) || !(barrier_std > kT) ||
       !(barrier_expl > kT) || !std::isfinite(theta0))
     return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   HIPCHK(launch_opes_init(ctx->stream, d_state, capacity, kT, sigma, barrier_std, barrier_expl, theta0));
   return ALCH_NB_OK;
 }
@@ -789,7 +815,7 @@ alch_nb_status alch_nb_opes_init(alch_nb_ctx* ctx, double* d_state, int32_t capa
 alch_nb_status alch_nb_opes_update(alch_nb_ctx* ctx, double* d_state, const double* d_dudl, double* d_lambda_out,
                                    int32_t deposit) {
   if (!ctx || !d_state) return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   HIPCHK(launch_opes(ctx->stream, d_state, d_dudl, d_lambda_out, deposit != 0));
   return ALCH_NB_OK;
 }
@@ -857,7 +883,7 @@ static void tune_cache_store(const std::string& key, int variant) {
 
 alch_nb_status alch_nb_autotune(alch_nb_ctx* ctx, const double* d_pos, const double* d_lambda, int32_t reps) {
   if (!ctx) return ALCH_NB_E_INVALID_ARG;
-  if (!ctx->bound) return ALCH_NB_E_NOT_BOUND;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   if (!d_pos || !d_lambda || reps < 1) return ALCH_NB_E_INVALID_ARG;
   alch_nb_status r = enqueue_compute(ctx, d_pos, d_lambda, ALCH_NB_AUTO_REBUILD, nullptr, false);
   if (r != ALCH_NB_OK) return r;

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "alch_nb.h"
 #include "anb_internal.h"
 
 namespace anb {
@@ -68,3 +69,8 @@ hipError_t launch_opes(hipStream_t st, double* state, const double* dudl, double
 inline double fixed_scale(int precision) { return precision == 0 ? 4294967296.0 : 1099511627776.0; }
 
 }  // namespace anb
+
+// Binding (alch_nb.cpp) and the library-owned device scratch (noalloc.hip).
+alch_nb_status anb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* stream, int static_device);
+bool anb_static_owns(const alch_nb_ctx* ctx, int device);
+void anb_static_release(const alch_nb_ctx* ctx);
