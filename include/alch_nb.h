@@ -81,7 +81,8 @@ enum {
   ALCH_NB_FLAG_LAMBDA_RANGE = 8u,   /* a lambda outside [0,1] was clamped */
   ALCH_NB_FLAG_CAPACITY = 16u,      /* the list did not fit its capacity; results of that call are invalid */
   ALCH_NB_FLAG_BARRIER_TIMEOUT = 32u,/* a list-build phase waited too long for the others; results invalid */
-  ALCH_NB_FLAG_BAD_INDEX = 64u       /* alch_nb_dihedrals met an atom index outside [0, N); that CV was skipped */
+  ALCH_NB_FLAG_BAD_INDEX = 64u,      /* alch_nb_dihedrals met an atom index outside [0, N); that CV was skipped */
+  ALCH_NB_FLAG_LD_CAPACITY = 128u    /* alch_nb_ld_step could not store an OPES kernel (capacity); it was dropped */
 };
 
 /* energy-term slots of alch_nb_out.terms, per system */
@@ -274,6 +275,65 @@ alch_nb_status alch_nb_opes_update(alch_nb_ctx *ctx, double *d_state, const doub
                                    int32_t deposit);
 /* Offsets of the state sections (host query, no HIP call); n >= 18. */
 alch_nb_status alch_nb_opes_layout(int32_t *offsets, int32_t n);
+
+/* Lambda dynamics with dual OPES and TI, and d-AFED extended dynamics
+ * (device, FP64), for the K boxes of the context.  The paper's extended
+ * Hamiltonian gives lambda (through the periodic theta of eq. 3) and the
+ * d-AFED variables s_k masses and thermostats of their own; OPES
+ * (eqs. 11-14) biases theta with kernels deposited every `stride` steps and
+ * compressed; dU/dlambda is binned along lambda for the free energy
+ * (eq. 2); s_k couples to the dihedral xi_k through eq. 15.  Integration:
+ * Langevin BAOAB (the paper names a regulated Nose-Hoover-Langevin
+ * thermostat without giving it), one step per call, the normal deviates
+ * taken from the caller's array.  Kernel compression: a new kernel within
+ * `compress` widths of the nearest centre is merged into it (weight, mean
+ * and variance conserved); rho_bar is the mean of rho_hat over the kernel
+ * centres.  Units: kcal/mol, fs, radians.
+ * alch_nb_ld_state_size: doubles of state for n_replicas (= K) boxes (-1 on
+ *   invalid parameters).
+ * alch_nb_ld_layout: offsets (doubles) into the state: [0] first replica
+ *   record, [1] record stride, [2] theta, [3] p_theta, [4] lambda (next),
+ *   [5] lambda (last step), [6] U_OPES, [7] dU_OPES/dtheta, [8] F_theta,
+ *   [9] steps done, [10] Standard kernel count, [11] Explore kernel count,
+ *   [12] Standard kernels (centres, weights, widths: capacity each),
+ *   [13] Explore kernels, [14] TI sums then counts (ti_bins each), all
+ *   within a record; [15] auxiliary section: s [n_cv] (for
+ *   alch_nb_dihedrals' d_s), [16] p_s, [17] last force on s; n >= 18.
+ * alch_nb_ld_init: clears d_state and sets theta0 [K] (device), and for
+ *   d-AFED s0, mass_s, kappa [n_cv] (device; NULL when n_cv = 0).
+ * alch_nb_ld_step: one step from d_dudl [K] (dU/dlambda at the current
+ *   lambda, e.g. alch_nb_out.dudl) and d_xi [n_cv] (the CVs at the current
+ *   positions; NULL when n_cv = 0), with the normal deviates of row
+ *   (step mod noise_rows) of d_noise [noise_rows][K + n_cv]; writes the
+ *   next lambda to d_lambda_out [K] (may be the array the next
+ *   alch_nb_compute reads).  A full kernel store raises
+ *   ALCH_NB_FLAG_LD_CAPACITY.
+ * alch_nb_ld_free_energy: Delta G per box by the midpoint rule over the
+ *   lambda bins (NaN while a bin has no sample) into d_out [K].
+ * All device pointers; work on the bound stream; FP64. */
+typedef struct {
+  int32_t capacity;           /* OPES kernels per variant and box (>= 1) */
+  int32_t stride;             /* deposition every stride steps (<= 0: no OPES) */
+  int32_t ti_bins;            /* lambda bins in [0, 1] (>= 1) */
+  int32_t n_cv;               /* d-AFED variables (0: lambda dynamics only) */
+  double kT;                  /* k_B T of theta, kcal/mol */
+  double mass;                /* theta mass, kcal/mol fs^2 (1 Da nm^2 = 239005.7) */
+  double friction;            /* theta friction, 1/fs */
+  double dt;                  /* time step, fs */
+  double sigma;               /* OPES kernel width on theta */
+  double barrier_std, barrier_expl; /* OPES barriers, kcal/mol (> kT) */
+  double compress;            /* merge threshold in kernel widths (0: no merging) */
+  double kT_s;                /* k_B T of the auxiliary variables, kcal/mol */
+  double friction_s;          /* their friction, 1/fs */
+} alch_nb_ld_params;
+int64_t alch_nb_ld_state_size(const alch_nb_ld_params *params, int32_t n_replicas);
+alch_nb_status alch_nb_ld_layout(const alch_nb_ld_params *params, int32_t n_replicas, int64_t *offsets, int32_t n);
+alch_nb_status alch_nb_ld_init(alch_nb_ctx *ctx, const alch_nb_ld_params *params, double *d_state,
+                               const double *d_theta0, const double *d_s0, const double *d_mass_s,
+                               const double *d_kappa);
+alch_nb_status alch_nb_ld_step(alch_nb_ctx *ctx, double *d_state, const double *d_dudl, const double *d_xi,
+                               const double *d_noise, int32_t noise_rows, double *d_lambda_out);
+alch_nb_status alch_nb_ld_free_energy(alch_nb_ctx *ctx, const double *d_state, double *d_out);
 
 /* Write the current list's pair set (i<j global indices, canonical FP64
  * test r^2 < (cutoff + skin)^2 at build time) to d_pairs [cap][2] in

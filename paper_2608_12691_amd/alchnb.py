@@ -20,7 +20,7 @@ BEUTLER_DSF, LBF_DSF = 0, 1
 FP32_FIXED, FP64 = 0, 1
 AUTO_REBUILD, FORCE_REBUILD = 1, 2
 FLAG_FIXED_OVERFLOW, FLAG_SKIN_EXCEEDED, FLAG_NONFINITE, FLAG_LAMBDA_RANGE, FLAG_CAPACITY = 1, 2, 4, 8, 16
-FLAG_BARRIER_TIMEOUT, FLAG_BAD_INDEX = 32, 64
+FLAG_BARRIER_TIMEOUT, FLAG_BAD_INDEX, FLAG_LD_CAPACITY = 32, 64, 128
 LIST_AUTO, LIST_PHASES, LIST_FUSED_ACTIVE = 0, 1, 2
 NTERMS = 10
 TERM_NAMES = ["E_solv_solv", "E_solu_solu", "E_ss_vdw", "E_ss_elec", "U_A", "U_B", "dUdl_vdw", "dUdl_elec",
@@ -33,7 +33,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "box too small", 3: "unsupported", 
 
 EXPORTED = ["alch_nb_create", "alch_nb_workspace_size", "alch_nb_bind", "alch_nb_bind_static", "alch_nb_build_list", "alch_nb_compute",
             "alch_nb_backward", "alch_nb_dihedrals", "alch_nb_opes_update", "alch_nb_opes_layout", "alch_nb_opes_init", "alch_nb_opes_state_size",
-            "alch_nb_export_pairs", "alch_nb_capture_step", "alch_nb_launch_step", "alch_nb_autotune",
+            "alch_nb_ld_state_size", "alch_nb_ld_layout", "alch_nb_ld_init", "alch_nb_ld_step",
+            "alch_nb_ld_free_energy", "alch_nb_export_pairs", "alch_nb_capture_step", "alch_nb_launch_step", "alch_nb_autotune",
             "alch_nb_set_variant", "alch_nb_num_variants", "alch_nb_set_list_mode", "alch_nb_get_list_mode",
             "alch_nb_set_timing", "alch_nb_get_flags",
             "alch_nb_get_stats", "alch_nb_destroy", "alch_nb_strerror", "alch_nb_last_hip_error",
@@ -70,6 +71,18 @@ class Grad_t(ctypes.Structure):
                 ("d_sqrt_epsilon", ctypes.c_void_p), ("d_charge", ctypes.c_void_p), ("d_epsilon", ctypes.c_void_p)]
 
 
+class LdParams_t(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int32), ("stride", ctypes.c_int32), ("ti_bins", ctypes.c_int32),
+                ("n_cv", ctypes.c_int32), ("kT", ctypes.c_double), ("mass", ctypes.c_double),
+                ("friction", ctypes.c_double), ("dt", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("barrier_std", ctypes.c_double), ("barrier_expl", ctypes.c_double), ("compress", ctypes.c_double),
+                ("kT_s", ctypes.c_double), ("friction_s", ctypes.c_double)]
+
+
+LD_LAYOUT = ["rep0", "rep_stride", "theta", "p", "lambda", "last_lambda", "u_opes", "du_opes", "f_theta", "n",
+             "n_std", "n_expl", "kern_std", "kern_expl", "ti", "cv_s", "cv_p", "cv_force"]
+
+
 class Stats_t(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int64), ("n_systems", ctypes.c_int64), ("n_superclusters", ctypes.c_int64),
                 ("n_entries", ctypes.c_int64), ("n_units", ctypes.c_int64), ("entry_capacity", ctypes.c_int64),
@@ -103,6 +116,11 @@ def load():
             "alch_nb_opes_layout": ([P, I32], I32),
             "alch_nb_opes_init": ([P, P, I32, D, D, D, D, D], I32),
             "alch_nb_opes_state_size": ([I32], I64),
+            "alch_nb_ld_state_size": ([P, I32], I64),
+            "alch_nb_ld_layout": ([P, I32, P, I32], I32),
+            "alch_nb_ld_init": ([P, P, P, P, P, P, P], I32),
+            "alch_nb_ld_step": ([P, P, P, P, P, I32, P], I32),
+            "alch_nb_ld_free_energy": ([P, P, P], I32),
             "alch_nb_export_pairs": ([P, P, I64, P], I32),
             "alch_nb_capture_step": ([P, P, P, P], I32),
             "alch_nb_launch_step": ([P], I32),
@@ -351,6 +369,62 @@ class Context:
         st = self.lib.alch_nb_opes_update(self.ctx, ctypes.c_void_p(state.data_ptr()), _addr(dudl),
                                           _addr(lam_out), int(bool(deposit)))
         self._check("alch_nb_opes_update", st)
+
+    # ------------------------------------------------------------ lambda dynamics
+    def ld_init(self, params, theta0, s0=None, mass_s=None, kappa=None):
+        """New lambda-dynamics state (device float64) for the context's K boxes.
+        params: dict of alch_nb_ld_params fields.  Returns (state, layout dict)."""
+        torch = self.torch
+        q = LdParams_t(**params)
+        n = int(self.lib.alch_nb_ld_state_size(ctypes.byref(q), self.K))
+        if n <= 0:
+            raise AlchNBError("alch_nb_ld_state_size", 1)
+        off = (ctypes.c_int64 * len(LD_LAYOUT))()
+        self._check("alch_nb_ld_layout", self.lib.alch_nb_ld_layout(ctypes.byref(q), self.K, off, len(LD_LAYOUT)))
+        state = torch.empty(n, dtype=torch.float64, device=self.device)
+        f64 = lambda a: None if a is None else torch.as_tensor(np.asarray(a, np.float64), dtype=torch.float64,
+                                                              device=self.device).contiguous()
+        th, s_, m_, k_ = f64(theta0), f64(s0), f64(mass_s), f64(kappa)
+        self._ld_keep = (th, s_, m_, k_)
+        self._check("alch_nb_ld_init", self.lib.alch_nb_ld_init(self.ctx, ctypes.byref(q), ctypes.c_void_p(state.data_ptr()),
+                                                                _addr(th), _addr(s_), _addr(m_), _addr(k_)))
+        lay = dict(zip(LD_LAYOUT, (int(v) for v in off)))
+        lay.update(capacity=q.capacity, ti_bins=q.ti_bins, n_cv=q.n_cv, K=self.K)
+        return state, lay
+
+    def ld_step(self, state, dudl, noise, lam_out, xi=None):
+        """One lambda-dynamics step; noise is a [rows, K + n_cv] float64 device tensor."""
+        st = self.lib.alch_nb_ld_step(self.ctx, ctypes.c_void_p(state.data_ptr()), ctypes.c_void_p(dudl.data_ptr()),
+                                      _addr(xi), ctypes.c_void_p(noise.data_ptr()), int(noise.shape[0]),
+                                      _addr(lam_out))
+        self._check("alch_nb_ld_step", st)
+
+    def ld_free_energy(self, state):
+        out = self.torch.empty(self.K, dtype=self.torch.float64, device=self.device)
+        self._check("alch_nb_ld_free_energy", self.lib.alch_nb_ld_free_energy(
+            self.ctx, ctypes.c_void_p(state.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    @staticmethod
+    def ld_view(state, lay):
+        """Host copy of a lambda-dynamics state as per-replica dicts and the auxiliary arrays."""
+        a = state.detach().cpu().numpy()
+        cap, nb, K, ncv = lay["capacity"], lay["ti_bins"], lay["K"], lay["n_cv"]
+        reps = []
+        for r in range(K):
+            b = lay["rep0"] + r * lay["rep_stride"]
+            rec = {k: a[b + lay[k]] for k in ("theta", "p", "lambda", "last_lambda", "u_opes", "du_opes", "f_theta")}
+            rec["n"] = int(a[b + lay["n"]])
+            for name, key, cnt in (("std", "kern_std", "n_std"), ("expl", "kern_expl", "n_expl")):
+                m = int(a[b + lay[cnt]])
+                k0 = b + lay[key]
+                rec[name] = (a[k0:k0 + m].copy(), a[k0 + cap:k0 + cap + m].copy(), a[k0 + 2 * cap:k0 + 2 * cap + m].copy())
+            t0 = b + lay["ti"]
+            rec["ti_sum"], rec["ti_cnt"] = a[t0:t0 + nb].copy(), a[t0 + nb:t0 + 2 * nb].copy()
+            reps.append(rec)
+        aux = dict(s=a[lay["cv_s"]:lay["cv_s"] + ncv].copy(), p=a[lay["cv_p"]:lay["cv_p"] + ncv].copy(),
+                   force=a[lay["cv_force"]:lay["cv_force"] + ncv].copy())
+        return reps, aux
 
     def export_pairs(self, cap=None):
         """Sorted int32 [m, 2] pair set of the current list (syncs)."""

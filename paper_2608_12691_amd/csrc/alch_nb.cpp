@@ -93,6 +93,7 @@ struct alch_nb_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   double tuned_ms = 0;  // tile time of the variant chosen by the autotuner
+  int ld_ncv = -1;       // auxiliary variables of the last lambda-dynamics state initialised (-1: none)
 };
 
 static alch_nb_status hip_fail(alch_nb_ctx* c, hipError_t e) {
@@ -817,6 +818,80 @@ alch_nb_status alch_nb_opes_update(alch_nb_ctx* ctx, double* d_state, const doub
   if (!ctx || !d_state) return ALCH_NB_E_INVALID_ARG;
   if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   HIPCHK(launch_opes(ctx->stream, d_state, d_dudl, d_lambda_out, deposit != 0));
+  return ALCH_NB_OK;
+}
+
+// ------------------------------------------------------------------ lambda dynamics
+
+static bool ld_params_ok(const alch_nb_ld_params* q) {
+  if (!q) return false;
+  if (q->capacity < 1 || q->ti_bins < 1 || q->n_cv < 0) return false;
+  if (!(q->kT > 0) || !(q->mass > 0) || !(q->friction >= 0) || !(q->dt > 0) || !(q->sigma > 0)) return false;
+  if (q->stride > 0 && (!(q->barrier_std > q->kT) || !(q->barrier_expl > q->kT))) return false;
+  if (!(q->compress >= 0)) return false;
+  if (q->n_cv > 0 && (!(q->kT_s > 0) || !(q->friction_s >= 0))) return false;
+  return (long long)q->capacity * 6 + 2LL * q->ti_bins < (1LL << 40);
+}
+
+int64_t alch_nb_ld_state_size(const alch_nb_ld_params* q, int32_t n_replicas) {
+  if (!ld_params_ok(q) || n_replicas < 1) return -1;
+  return ld_state_words(n_replicas, q->n_cv, q->capacity, q->ti_bins);
+}
+
+alch_nb_status alch_nb_ld_layout(const alch_nb_ld_params* q, int32_t n_replicas, int64_t* o, int32_t n) {
+  if (!ld_params_ok(q) || n_replicas < 1 || !o || n < 18) return ALCH_NB_E_INVALID_ARG;
+  const long long rw = ld_rep_words(q->capacity, q->ti_bins);
+  const long long cv = LD_HEADER + n_replicas * rw;
+  const int64_t v[18] = {LD_HEADER, rw, LD_R_THETA, LD_R_P, LD_R_LAMBDA, LD_R_LAST_LAMBDA, LD_R_U, LD_R_DU,
+                         LD_R_FTHETA, LD_R_N, LD_R_NSTD, LD_R_NEXPL, LD_REP_HEADER, LD_REP_HEADER + 3LL * q->capacity,
+                         LD_REP_HEADER + 6LL * q->capacity, cv + LD_C_HEADER, cv + LD_C_HEADER + q->n_cv,
+                         cv + LD_C_HEADER + 4LL * q->n_cv};
+  for (int i = 0; i < 18; ++i) o[i] = v[i];
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_ld_init(alch_nb_ctx* ctx, const alch_nb_ld_params* q, double* d_state, const double* d_theta0,
+                               const double* d_s0, const double* d_mass_s, const double* d_kappa) {
+  if (!ctx || !ld_params_ok(q) || !d_state || !d_theta0) return ALCH_NB_E_INVALID_ARG;
+  if (q->n_cv > 0 && (!d_s0 || !d_mass_s || !d_kappa)) return ALCH_NB_E_INVALID_ARG;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
+  LdInit in{};
+  in.K = ctx->K;
+  in.n_cv = q->n_cv;
+  in.cap = q->capacity;
+  in.bins = q->ti_bins;
+  in.stride = q->stride;
+  in.kT = q->kT;
+  in.mass = q->mass;
+  in.gamma = q->friction;
+  in.dt = q->dt;
+  in.sigma = q->sigma;
+  in.compress = q->compress;
+  in.kT_s = q->kT_s;
+  in.gamma_s = q->friction_s;
+  in.de_std = q->barrier_std;
+  in.de_expl = q->barrier_expl;
+  HIPCHK(launch_ld_init(ctx->stream, d_state, ld_state_words(ctx->K, q->n_cv, q->capacity, q->ti_bins), in, d_theta0,
+                        d_s0, d_mass_s, d_kappa));
+  ctx->ld_ncv = q->n_cv;
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_ld_step(alch_nb_ctx* ctx, double* d_state, const double* d_dudl, const double* d_xi,
+                               const double* d_noise, int32_t noise_rows, double* d_lambda_out) {
+  if (!ctx || !d_state || !d_dudl || !d_noise || noise_rows < 1) return ALCH_NB_E_INVALID_ARG;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
+  if (ctx->ld_ncv < 0) return ALCH_NB_E_NOT_BOUND;  // no state initialised
+  if ((ctx->ld_ncv > 0) != (d_xi != nullptr)) return ALCH_NB_E_INVALID_ARG;
+  HIPCHK(launch_ld_step(ctx->stream, d_state, ctx->K, ctx->ld_ncv, d_dudl, d_xi, d_noise, noise_rows, d_lambda_out,
+                        ctx->dev.flags));
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_ld_free_energy(alch_nb_ctx* ctx, const double* d_state, double* d_out) {
+  if (!ctx || !d_state || !d_out) return ALCH_NB_E_INVALID_ARG;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
+  HIPCHK(launch_ld_free_energy(ctx->stream, d_state, ctx->K, d_out));
   return ALCH_NB_OK;
 }
 

@@ -156,6 +156,32 @@ struct Dev {
   const double* pot64;       // [kPot64Words] FP64 potential constants of the solute units (see pot64_words)
 };
 
+// Lambda-dynamics state (doubles): a header, one record per replica (theta
+// and its OPES kernels and TI bins), then the auxiliary-variable section.
+enum {
+  LD_K = 0, LD_NCV = 1, LD_CAP = 2, LD_BINS = 3, LD_STRIDE = 4, LD_KT = 5, LD_MASS = 6, LD_GAMMA = 7, LD_DT = 8,
+  LD_SIGMA = 9, LD_COMPRESS = 10, LD_KT_S = 11, LD_GAMMA_S = 12, LD_DE_STD = 13, LD_DE_EXPL = 14, LD_HEADER = 16
+};
+// per replica: header, then Standard kernels (centres, weights, widths:
+// cap each), Explore kernels (same), TI sums and counts (bins each)
+enum {
+  LD_R_THETA = 0, LD_R_P = 1, LD_R_LAMBDA = 2, LD_R_LAST_LAMBDA = 3, LD_R_DLAM = 4, LD_R_U = 5, LD_R_DU = 6,
+  LD_R_FTHETA = 7, LD_R_N = 8, LD_R_NSTD = 9, LD_R_NEXPL = 10, LD_R_RBAR_STD = 11, LD_R_RBAR_EXPL = 12,
+  LD_REP_HEADER = 16
+};
+// auxiliary section: step count, then s, p, mass, kappa, last force (n_cv each)
+enum { LD_C_N = 0, LD_C_HEADER = 8 };
+__host__ __device__ inline long long ld_rep_words(int cap, int bins) {
+  return LD_REP_HEADER + 6LL * cap + 2LL * bins;
+}
+__host__ __device__ inline long long ld_state_words(int K, int n_cv, int cap, int bins) {
+  return LD_HEADER + (long long)K * ld_rep_words(cap, bins) + LD_C_HEADER + 5LL * n_cv;
+}
+struct LdInit {
+  int K, n_cv, cap, bins, stride;
+  double kT, mass, gamma, dt, sigma, compress, kT_s, gamma_s, de_std, de_expl;
+};
+
 enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6 };
 
 constexpr int kMaxTypes = 256;  // atom types supported by the parameter-gradient pass

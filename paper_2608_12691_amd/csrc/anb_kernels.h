@@ -68,6 +68,12 @@ hipError_t launch_opes(hipStream_t st, double* state, const double* dudl, double
 // Fixed-point scale of the force accumulators (units per kcal/mol/A).
 inline double fixed_scale(int precision) { return precision == 0 ? 4294967296.0 : 1099511627776.0; }
 
+hipError_t launch_ld_init(hipStream_t st, double* state, long long words, const LdInit& in, const double* theta0,
+                          const double* s0, const double* mass_s, const double* kappa);
+hipError_t launch_ld_step(hipStream_t st, double* state, int K, int n_cv, const double* dudl, const double* xi,
+                          const double* noise, int noise_rows, double* lam_out, unsigned int* flags);
+hipError_t launch_ld_free_energy(hipStream_t st, const double* state, int K, double* out);
+
 }  // namespace anb
 
 // Binding (alch_nb.cpp) and the library-owned device scratch (noalloc.hip).
