@@ -335,6 +335,36 @@ alch_nb_status alch_nb_ld_step(alch_nb_ctx *ctx, double *d_state, const double *
                                const double *d_noise, int32_t noise_rows, double *d_lambda_out);
 alch_nb_status alch_nb_ld_free_energy(alch_nb_ctx *ctx, const double *d_state, double *d_out);
 
+/* Replica exchange between lambda states (LBF schedule only; the paper's
+ * HREX reference protocol, Simulation Details): box r holds state
+ * d_state_of[r] of the ascending d_lambda_states [K]; with the LBF potential
+ * linear in its bases (eq. 4) the basis energies U_A, U_B of each box (the
+ * terms of the last alch_nb_compute, d_terms [K][ALCH_NB_NTERMS]) give every
+ * neighbour swap's D = [U_a(l_s+1) - U_a(l_s) + U_b(l_s) - U_b(l_s+1)]/kT;
+ * the swap is accepted when D <= 0 or u < exp(-D).  Attempt n (counted in
+ * d_stats[0]) pairs the states (s, s+1) with s of parity n mod 2 and takes
+ * pair s's uniform deviate from row (n mod rows) of d_uniform [rows][K-1];
+ * d_lambda [K] is rewritten with each box's new state's lambda (it may be
+ * the array the next alch_nb_compute reads).  d_stats [2K-1] int64:
+ * attempts so far, then attempts and accepts per pair (K-1 each).
+ * alch_nb_hrex_init sets d_state_of to the identity and clears d_stats.
+ * ALCH_NB_E_UNSUPPORTED for the Beutler schedule (its cross-state energies
+ * need evaluations at the other lambdas) or K outside [2, 4096].  Device
+ * pointers; work on the bound stream. */
+alch_nb_status alch_nb_hrex_init(alch_nb_ctx *ctx, int32_t *d_state_of, int64_t *d_stats);
+alch_nb_status alch_nb_hrex_exchange(alch_nb_ctx *ctx, const double *d_terms, const double *d_lambda_states,
+                                     int32_t *d_state_of, double *d_lambda, const double *d_uniform, int32_t rows,
+                                     double kT, int64_t *d_stats);
+
+/* Record every call made between alch_nb_capture_begin() and
+ * alch_nb_capture_end() on the bound stream (e.g. alch_nb_compute,
+ * alch_nb_dihedrals, alch_nb_ld_step, alch_nb_hrex_exchange) as one HIP
+ * graph, replayed with alch_nb_launch_step(); the pointers are captured.
+ * Calls that synchronize (flags, statistics, pair export) are not allowed
+ * in between. */
+alch_nb_status alch_nb_capture_begin(alch_nb_ctx *ctx);
+alch_nb_status alch_nb_capture_end(alch_nb_ctx *ctx);
+
 /* Write the current list's pair set (i<j global indices, canonical FP64
  * test r^2 < (cutoff + skin)^2 at build time) to d_pairs [cap][2] in
  * unspecified order and its size to the host *n_out; syncs the stream.

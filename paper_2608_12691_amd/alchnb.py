@@ -34,7 +34,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "box too small", 3: "unsupported", 
 EXPORTED = ["alch_nb_create", "alch_nb_workspace_size", "alch_nb_bind", "alch_nb_bind_static", "alch_nb_build_list", "alch_nb_compute",
             "alch_nb_backward", "alch_nb_dihedrals", "alch_nb_opes_update", "alch_nb_opes_layout", "alch_nb_opes_init", "alch_nb_opes_state_size",
             "alch_nb_ld_state_size", "alch_nb_ld_layout", "alch_nb_ld_init", "alch_nb_ld_step",
-            "alch_nb_ld_free_energy", "alch_nb_export_pairs", "alch_nb_capture_step", "alch_nb_launch_step", "alch_nb_autotune",
+            "alch_nb_ld_free_energy", "alch_nb_hrex_init", "alch_nb_hrex_exchange", "alch_nb_capture_begin",
+            "alch_nb_capture_end", "alch_nb_export_pairs", "alch_nb_capture_step", "alch_nb_launch_step", "alch_nb_autotune",
             "alch_nb_set_variant", "alch_nb_num_variants", "alch_nb_set_list_mode", "alch_nb_get_list_mode",
             "alch_nb_set_timing", "alch_nb_get_flags",
             "alch_nb_get_stats", "alch_nb_destroy", "alch_nb_strerror", "alch_nb_last_hip_error",
@@ -121,6 +122,10 @@ def load():
             "alch_nb_ld_init": ([P, P, P, P, P, P, P], I32),
             "alch_nb_ld_step": ([P, P, P, P, P, I32, P], I32),
             "alch_nb_ld_free_energy": ([P, P, P], I32),
+            "alch_nb_hrex_init": ([P, P, P], I32),
+            "alch_nb_hrex_exchange": ([P, P, P, P, P, P, I32, D, P], I32),
+            "alch_nb_capture_begin": ([P], I32),
+            "alch_nb_capture_end": ([P], I32),
             "alch_nb_export_pairs": ([P, P, I64, P], I32),
             "alch_nb_capture_step": ([P, P, P, P], I32),
             "alch_nb_launch_step": ([P], I32),
@@ -425,6 +430,30 @@ class Context:
         aux = dict(s=a[lay["cv_s"]:lay["cv_s"] + ncv].copy(), p=a[lay["cv_p"]:lay["cv_p"] + ncv].copy(),
                    force=a[lay["cv_force"]:lay["cv_force"] + ncv].copy())
         return reps, aux
+
+    # ------------------------------------------------------------ replica exchange
+    def hrex_init(self):
+        """(state_of int32 [K], stats int64 [2K-1]) device tensors, identity assignment."""
+        torch = self.torch
+        so = torch.empty(self.K, dtype=torch.int32, device=self.device)
+        stt = torch.empty(2 * self.K - 1, dtype=torch.int64, device=self.device)
+        self._check("alch_nb_hrex_init", self.lib.alch_nb_hrex_init(self.ctx, ctypes.c_void_p(so.data_ptr()),
+                                                                    ctypes.c_void_p(stt.data_ptr())))
+        return so, stt
+
+    def hrex_exchange(self, terms, lambda_states, state_of, lam, uniform, kT, stats):
+        st = self.lib.alch_nb_hrex_exchange(self.ctx, ctypes.c_void_p(terms.data_ptr()),
+                                            ctypes.c_void_p(lambda_states.data_ptr()),
+                                            ctypes.c_void_p(state_of.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                            ctypes.c_void_p(uniform.data_ptr()), int(uniform.shape[0]), float(kT),
+                                            ctypes.c_void_p(stats.data_ptr()))
+        self._check("alch_nb_hrex_exchange", st)
+
+    def capture_begin(self):
+        self._check("alch_nb_capture_begin", self.lib.alch_nb_capture_begin(self.ctx))
+
+    def capture_end(self):
+        self._check("alch_nb_capture_end", self.lib.alch_nb_capture_end(self.ctx))
 
     def export_pairs(self, cap=None):
         """Sorted int32 [m, 2] pair set of the current list (syncs)."""

@@ -38,6 +38,7 @@ constexpr bool variants_fit() {
     if (v.epu < 1 || v.epu > kMaxEpu) return false;
   return true;
 }
+static_assert(ALCH_NB_NTERMS == NTERMS_DEV, "terms per box");
 static_assert(variants_fit(), "the tile kernel stages the j-forces of at most kMaxEpu entries per unit");
 constexpr int kTimingSlots = 4096;
 
@@ -94,6 +95,7 @@ struct alch_nb_ctx {
   hipGraphExec_t gexec = nullptr;
   double tuned_ms = 0;  // tile time of the variant chosen by the autotuner
   int ld_ncv = -1;       // auxiliary variables of the last lambda-dynamics state initialised (-1: none)
+  bool capturing = false;  // between alch_nb_capture_begin and _end (no timing events then)
 };
 
 static alch_nb_status hip_fail(alch_nb_ctx* c, hipError_t e) {
@@ -622,7 +624,7 @@ alch_nb_status alch_nb_compute(alch_nb_ctx* ctx, const double* d_pos, const doub
   if (!ctx) return ALCH_NB_E_INVALID_ARG;
   if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   if (!d_pos || !d_lambda) return ALCH_NB_E_INVALID_ARG;
-  return enqueue_compute(ctx, d_pos, d_lambda, flags, out, true);
+  return enqueue_compute(ctx, d_pos, d_lambda, flags, out, !ctx->capturing);
 }
 
 alch_nb_status alch_nb_build_list(alch_nb_ctx* ctx, const double* d_pos) {
@@ -892,6 +894,50 @@ alch_nb_status alch_nb_ld_free_energy(alch_nb_ctx* ctx, const double* d_state, d
   if (!ctx || !d_state || !d_out) return ALCH_NB_E_INVALID_ARG;
   if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
   HIPCHK(launch_ld_free_energy(ctx->stream, d_state, ctx->K, d_out));
+  return ALCH_NB_OK;
+}
+
+// ------------------------------------------------------------------ replica exchange
+
+alch_nb_status alch_nb_hrex_init(alch_nb_ctx* ctx, int32_t* d_state_of, int64_t* d_stats) {
+  if (!ctx || !d_state_of || !d_stats) return ALCH_NB_E_INVALID_ARG;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
+  if (ctx->K < 2 || ctx->K > kHrexMax) return ALCH_NB_E_UNSUPPORTED;
+  HIPCHK(launch_hrex_init(ctx->stream, d_state_of, reinterpret_cast<long long*>(d_stats), ctx->K));
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_hrex_exchange(alch_nb_ctx* ctx, const double* d_terms, const double* d_lambda_states,
+                                     int32_t* d_state_of, double* d_lambda, const double* d_uniform, int32_t rows,
+                                     double kT, int64_t* d_stats) {
+  if (!ctx || !d_terms || !d_lambda_states || !d_state_of || !d_lambda || !d_uniform || rows < 1 || !(kT > 0) ||
+      !d_stats)
+    return ALCH_NB_E_INVALID_ARG;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
+  if (ctx->p.schedule != ALCH_NB_LBF_DSF || ctx->K < 2 || ctx->K > kHrexMax) return ALCH_NB_E_UNSUPPORTED;
+  HIPCHK(launch_hrex(ctx->stream, d_terms, d_lambda_states, d_state_of, d_lambda, d_uniform, rows, kT,
+                     reinterpret_cast<long long*>(d_stats), ctx->K));
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_capture_begin(alch_nb_ctx* ctx) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
+  if (!ctx->stream) return ALCH_NB_E_UNSUPPORTED;
+  destroy_graph(ctx);
+  HIPCHK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  ctx->capturing = true;
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_capture_end(alch_nb_ctx* ctx) {
+  if (!ctx) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->stream) return ALCH_NB_E_UNSUPPORTED;
+  hipGraph_t g = nullptr;
+  ctx->capturing = false;
+  HIPCHK(hipStreamEndCapture(ctx->stream, &g));
+  ctx->graph = g;
+  HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
   return ALCH_NB_OK;
 }
 

@@ -156,6 +156,10 @@ struct Dev {
   const double* pot64;       // [kPot64Words] FP64 potential constants of the solute units (see pot64_words)
 };
 
+// Replica exchange: boxes per context it handles, and the terms per box.
+constexpr int kHrexMax = 4096;
+constexpr int NTERMS_DEV = 10;
+
 // Lambda-dynamics state (doubles): a header, one record per replica (theta
 // and its OPES kernels and TI bins), then the auxiliary-variable section.
 enum {

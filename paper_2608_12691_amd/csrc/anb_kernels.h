@@ -72,6 +72,9 @@ hipError_t launch_ld_init(hipStream_t st, double* state, long long words, const 
                           const double* s0, const double* mass_s, const double* kappa);
 hipError_t launch_ld_step(hipStream_t st, double* state, int K, int n_cv, const double* dudl, const double* xi,
                           const double* noise, int noise_rows, double* lam_out, unsigned int* flags);
+hipError_t launch_hrex_init(hipStream_t st, int* state_of, long long* stats, int K);
+hipError_t launch_hrex(hipStream_t st, const double* terms, const double* lam_states, int* state_of, double* lam_out,
+                       const double* uniform, int rows, double kT, long long* stats, int K);
 hipError_t launch_ld_free_energy(hipStream_t st, const double* state, int K, double* out);
 
 }  // namespace anb

@@ -23,6 +23,7 @@
 #include "anb_kernels.h"
 #include "erfc_coeffs.h"
 #include "lane_ops.h"
+#include "pair_math.h"
 
 namespace anb {
 
@@ -42,18 +43,6 @@ template <>
 __device__ inline double rsq_(double x) {
   return 1.0 / sqrt(x);
 }
-__device__ inline void erfc_exp_(float x, float& ec, float& ex) {
-  const float t = __builtin_amdgcn_rcpf(fmaf(ANB_ERFC_P, x, 1.0f));
-  float p = kErfcCoef[ANB_ERFC_DEG];
-#pragma unroll
-  for (int k = ANB_ERFC_DEG - 1; k >= 0; --k) p = fmaf(p, t, kErfcCoef[k]);
-  ex = __builtin_amdgcn_exp2f((x * x) * -1.4426950408889634f);
-  ec = t * p * ex;
-}
-__device__ inline void erfc_exp_(double x, double& ec, double& ex) {
-  ex = exp(-x * x);
-  ec = erfc(x);
-}
 
 // Derivatives of one pair energy with respect to the combined parameters
 // sigma_ij, eps_ij and (q_i q_j) (raw charges).
@@ -70,7 +59,7 @@ __device__ inline void pair_param_derivs(R r2, bool alch, R sg, R e4, R inv_s6, 
     S = R(1) - t * t * t * (R(10) + t * (R(-15) + R(6) * t));
   }
   R ec, ex;
-  erfc_exp_((R)pc.alpha * r, ec, ex);
+  erfc_exp((R)pc.alpha * r, ec, ex);
   const R D = (R)kKe * (ec * rinv - (R)pc.A + (R)pc.B * (r - (R)pc.rc));
   const R isg = rcp_(sg);
   if (!alch) {

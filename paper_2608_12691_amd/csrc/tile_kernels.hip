@@ -27,6 +27,7 @@
 #include "anb_kernels.h"
 #include "erfc_coeffs.h"
 #include "lane_ops.h"
+#include "pair_math.h"
 
 namespace anb {
 
@@ -46,19 +47,6 @@ __device__ inline double rcp(double x) { return 1.0 / x; }
 __device__ inline float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 __device__ inline double clamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
 
-// erfc(x) and exp(-x^2) for 0 <= x <= ANB_ERFC_XMAX
-__device__ inline void erfc_exp(float x, float& ec, float& ex) {
-  const float t = __builtin_amdgcn_rcpf(fmaf(ANB_ERFC_P, x, 1.0f));
-  float p = kErfcCoef[ANB_ERFC_DEG];
-#pragma unroll
-  for (int k = ANB_ERFC_DEG - 1; k >= 0; --k) p = fmaf(p, t, kErfcCoef[k]);
-  ex = __builtin_amdgcn_exp2f((x * x) * -1.4426950408889634f);
-  ec = t * p * ex;
-}
-__device__ inline void erfc_exp(double x, double& ec, double& ex) {
-  ex = exp(-x * x);
-  ec = erfc(x);
-}
 __constant__ double kErfc64ChebDev[ANB_ERFC64_DEG + 1] = {
 #define X(i) kErfc64Cheb[i]
   X(0), X(1), X(2), X(3), X(4), X(5), X(6), X(7), X(8), X(9), X(10), X(11), X(12), X(13), X(14), X(15), X(16)
@@ -920,20 +908,7 @@ __global__ void __launch_bounds__(kBlk) k_prepare(Dev d, const double* __restric
       s.a[2] = l <= 0.5 ? 2.0 : 0.0;
       s.a[3] = l > 0.5 ? 2.0 : 0.0;
     } else {
-      // hA = S32((l - 0.35)/0.65), hB = S22(l) - hA (the paper's eqs. 7-10)
-      const double x = (l - 0.35) / 0.65;
-      double hA = 0.0, dhA = 0.0;
-      if (x > 0.0) {
-        const double xc = fmin(x, 1.0);
-        hA = xc * xc * xc * xc * (15.0 + xc * (-24.0 + 10.0 * xc));
-        dhA = x < 1.0 ? 60.0 * xc * xc * xc * (1.0 - xc) * (1.0 - xc) / 0.65 : 0.0;
-      }
-      const double s22 = l * l * l * (10.0 + l * (-15.0 + 6.0 * l));
-      const double ds22 = 30.0 * l * l * (1.0 - l) * (1.0 - l);
-      s.a[0] = hA;
-      s.a[1] = s22 - hA;
-      s.a[2] = dhA;
-      s.a[3] = ds22 - dhA;
+      lbf_switch(l, s.a[0], s.a[1], s.a[2], s.a[3]);
     }
     for (int k = 0; k < 4; ++k) s.f[k] = (float)s.a[k];
     d.lam[t] = s;

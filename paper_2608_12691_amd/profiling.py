@@ -21,7 +21,7 @@ import sys
 import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ("tile_kernels.hip", "anb_internal.h", "erfc_coeffs.h", "lane_ops.h")
+KERNEL_SOURCES = ("tile_kernels.hip", "anb_internal.h", "erfc_coeffs.h", "lane_ops.h", "pair_math.h")
 
 
 def kernel_source_hash():
