@@ -330,18 +330,19 @@ __device__ inline Pot<double> load_pot64(const double* w) {
 // One unit of a solute super-cluster, by the whole wave, in FP64 from FP64
 // inputs: its entries are the solute-solute pairs (plain) and the
 // solute-solvent pairs (soft core or LBF), the only pairs that dU/dlambda
-// and the solute terms sum over.  Lane (jl, il) takes j-atom jl of an
-// entry's j-cluster and, for each i-cluster c of its mask, i-atom il.  Each
-// pair's parameters come from its two slots' FP64 values (sigma/2,
-// 2 sqrt(eps), and q sqrt(k_e) beside the position), so a tile needs one
-// round of independent loads.  j-forces are summed over the i-clusters and
-// il, i-forces over jl, and both leave as 64-bit fixed-point atomics (a few
-// per entry: these units are small).  The unit's sums go to its
-// accumulator slots.  kCheb: erfc from the Chebyshev series (few
-// registers; the FP32 kernel) or the library (the FP64 kernel).
+// and the solute terms sum over.  The super-cluster's 64 slots (FP64
+// position, q sqrt(k_e), sigma/2, 2 sqrt(eps)) are staged in the wave's LDS
+// slice `si` (six arrays of 64), one load per lane; lane (jl, il) then takes
+// j-atom jl of an entry's j-cluster (loaded one entry ahead) and, for each
+// i-cluster c of its mask, i-atom il from LDS.  Pair parameters follow the
+// combination rule from the per-slot FP64 values.  j-forces are summed over
+// the i-clusters and il, i-forces over jl, and both leave as 64-bit
+// fixed-point atomics (a few per entry: these units are small).  The unit's
+// sums go to its accumulator slots.  kCheb: erfc from the Chebyshev series
+// (few registers; the FP32 kernel) or the library (the FP64 kernel).
 template <int SCHED, bool SW, bool kCheb>
 __device__ inline void solute_unit(const Dev& d, const Pot<double>& P, const float4* dsf, const int4& U, int u,
-                                   double fscale) {
+                                   double fscale, double* const* si) {
   const int lane = threadIdx.x & 63;
   const int il = lane & 7, jl = lane >> 3;
   const int s = U.x;
@@ -349,29 +350,50 @@ __device__ inline void solute_unit(const Dev& d, const Pot<double>& P, const flo
   const LamState lam = d.lam[unit_rep(U.w)];
   const cptr<uint32_t> einfo = as_const(d.ent_info);
   const cptr<unsigned long long> emask = as_const(d.ent_mask);
+  // j-data of entry e: position moved into the i-super-cluster's frame, q, sigma/2, 2 sqrt(eps)
+  double4 nj = make_double4(0.0, 0.0, 0.0, 0.0);
+  double2 nje = make_double2(0.0, 0.0);
+  int njsl = 0;
+  auto load_j = [&](int e) {
+    njsl = d.ent_jc[e] * kCl + jl;
+    const double4 off = d.ent_off[e];
+    const double4 pj = d.pos64[njsl];
+    nje = d.se64[njsl];
+    nj = make_double4(pj.x + off.x, pj.y + off.y, pj.z + off.z, pj.w);
+  };
+  if (U.y < U.z) load_j(U.y);  // in flight while the slots are staged
+  {
+    const double4 pi = d.pos64[s * kSc + lane];  // .w: q sqrt(k_e)
+    const double2 ei = d.se64[s * kSc + lane];   // sigma/2, 2 sqrt(eps)
+    wave_sync();
+    si[0][lane] = pi.x;
+    si[1][lane] = pi.y;
+    si[2][lane] = pi.z;
+    si[3][lane] = pi.w;
+    si[4][lane] = ei.x;
+    si[5][lane] = ei.y;
+    wave_sync();
+  }
   double e_solu = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
   int npair = 0;
   for (int e = U.y; e < U.z; ++e) {
+    const double4 pj = nj;
+    const double2 ej = nje;
+    const int jsl = njsl;
+    if (e + 1 < U.z) load_j(e + 1);
     const uint32_t info = einfo[e];
     const uint32_t imask = info & 0xffu;
     const bool alch = ((info >> 8) & 3u) == (uint32_t)KIND_ALCH;
-    const int jsl = d.ent_jc[e] * kCl + jl;
-    const double4 off = d.ent_off[e];
-    const double4 pj = d.pos64[jsl];  // .w: q sqrt(k_e)
-    const double2 ej = d.se64[jsl];   // sigma/2, 2 sqrt(eps)
-    const double xj = pj.x + off.x, yj = pj.y + off.y, zj = pj.z + off.z;
     double fjx = 0.0, fjy = 0.0, fjz = 0.0;
 #pragma unroll 1
     for (int c = 0; c < kScCl; ++c) {
       if (!(imask & (1u << c))) continue;
-      const int isl = s * kSc + c * kCl + il;
-      const double4 pi = d.pos64[isl];
-      const double2 ei = d.se64[isl];
-      const double dx = xj - pi.x, dy = yj - pi.y, dz = zj - pi.z;
-      const double sij = ei.x + ej.x;
+      const int src = c * kCl + il;
+      const double dx = pj.x - si[0][src], dy = pj.y - si[1][src], dz = pj.z - si[2][src];
+      const double sij = si[4][src] + ej.x;
       // padding slots carry sigma 0 (their lanes are masked out)
       const double s2 = sij > 0.0 ? sij * sij : 1.0;
-      const double4 tp = make_double4(sij, ei.y * ej.y, pi.w * pj.w, 1.0 / (s2 * s2 * s2));
+      const double4 tp = make_double4(sij, si[5][src] * ej.y, si[3][src] * pj.w, 1.0 / (s2 * s2 * s2));
       const bool valid = __builtin_amdgcn_inverse_ballot_w64(emask[(size_t)e * kScCl + c]);
       const double r2 = dx * dx + dy * dy + dz * dz;
       const bool inr = valid && r2 < P.rc2;
@@ -385,14 +407,14 @@ __device__ inline void solute_unit(const Dev& d, const Pot<double>& P, const flo
         fr = pc.flj0 * pc.S - pc.lj0 * pc.rdS + pc.fel;
         if (inr) e_solu += uu;
       }
-      const double rinv2 = pc.rinv2;
       npair += __popcll(__ballot(inr));
-      const double fs = inr ? fr * rinv2 : 0.0;
+      const double fs = inr ? fr * pc.rinv2 : 0.0;
       const double fx = fs * dx, fy = fs * dy, fz = fs * dz;
       fjx += fx;
       fjy += fy;
       fjz += fz;
       const double gx = red_jl(fx), gy = red_jl(fy), gz = red_jl(fz);
+      const int isl = s * kSc + src;
       add_fixed_lanes(d.ffix + isl, -gx, fscale, d.flags, jl == 0);
       add_fixed_lanes(d.ffix + slots + isl, -gy, fscale, d.flags, jl == 0);
       add_fixed_lanes(d.ffix + 2 * slots + isl, -gz, fscale, d.flags, jl == 0);
@@ -418,6 +440,7 @@ __device__ inline void solute_unit(const Dev& d, const Pot<double>& P, const flo
     o[ACC_A2 * UC] = a2;
     o[ACC_NPAIR * UC] = (double)npair;
   }
+  wave_sync();  // the LDS slice is the unit loop's next
 }
 
 template <typename R, int SCHED, bool SW>
@@ -451,6 +474,12 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   double* rare1 = &rare_all[1][threadIdx.x];  // a0 .. a2 of the alchemical pairs
   double* rare2 = &rare_all[2][threadIdx.x];
   double* rare3 = &rare_all[3][threadIdx.x];
+  // the solute phase (before the unit loop uses LDS) stages its super-cluster's
+  // FP64 slot data in this wave's slices of rare_all and jpos_all
+  double* const sol_lds[6] = {&rare_all[0][threadIdx.x & ~63], &rare_all[1][threadIdx.x & ~63],
+                              &rare_all[2][threadIdx.x & ~63], &rare_all[3][threadIdx.x & ~63],
+                              reinterpret_cast<double*>(jpos_all + (threadIdx.x & ~63)),
+                              reinterpret_cast<double*>(jpos_all + (threadIdx.x & ~63)) + 64};
   P4* ipos = ipos_all + (threadIdx.x & ~63);
   P2* ise = ise_all + (threadIdx.x & ~63);
   // i-forces of the solute-solvent entries of the current super-cluster,
@@ -527,16 +556,21 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     return make_int4(__builtin_amdgcn_readlane(hdr.x, i), __builtin_amdgcn_readlane(hdr.y, i),
                      __builtin_amdgcn_readlane(hdr.z, i), __builtin_amdgcn_readlane(hdr.w, i));
   };
-  // Solute units first, in FP64, before the FP32 state below is live
+  // Solute units first, in FP64, before the FP32 state below is live; a
+  // wave left with nothing else ends here (the loop below would only load
+  // and flush an empty super-cluster)
   if (nr > 0) load_hdrs(0);
+  int n_sol = 0;
   for (int r = 0; r < nr; ++r) {
     if (r > 0 && (r & 63) == 0) load_hdrs(r);
     const int4 V = header(r);
     if (__builtin_expect((V.w & kUnitSolute) != 0, 0)) {
       const Pot<double> P64 = load_pot64(d.pot64);
-      solute_unit<SCHED, SW, sizeof(R) == 4>(d, P64, dsf, V, ub + r, fscale);
+      solute_unit<SCHED, SW, sizeof(R) == 4>(d, P64, dsf, V, ub + r, fscale, sol_lds);
+      ++n_sol;
     }
   }
+  if (n_sol == nr) return;
   int n_jc = 0;
   uint32_t n_inf = 0;
   double4 n_off = make_double4(0.0, 0.0, 0.0, 0.0);
