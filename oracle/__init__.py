@@ -6,7 +6,9 @@ library and the GPU library never imports it.
 
 ``alch_oracle.c`` holds the FP64 O(N^2) pair loop; ``opes.py`` and
 ``dihedral.py`` hold the FP64 reference for the lambda/OPES bias update and
-the dihedral collective variables.
+the dihedral collective variables; ``ldyn.py`` and ``hrex.py`` the lambda
+and d-AFED dynamics and the replica exchange; ``pme.py`` the particle-mesh
+Ewald reciprocal space with the lambda-scaled solute-solvent cross term.
 """
 from __future__ import annotations
 
@@ -24,6 +26,7 @@ _lock = threading.Lock()
 _lib = None
 
 BEUTLER, LBF = 0, 1
+EWALD_REAL = 4
 TERM_NAMES = ["E_solv_solv", "E_solu_solu", "E_ss_vdw", "E_ss_elec", "U_A", "U_B",
               "dUdl_vdw", "dUdl_elec", "E_total", "dUdl_total"]
 NTERMS = len(TERM_NAMES)
@@ -62,6 +65,7 @@ def _load():
             lib.oracle_ucap.argtypes = [d, P]
             lib.oracle_switch.argtypes = [d, d, d, P]
             lib.oracle_dsf.argtypes = [d, d, d, P]
+            lib.oracle_ewald_real.argtypes = [d, d, P]
             _lib = lib
     return _lib
 
@@ -77,12 +81,18 @@ def _c(a, dtype):
 class Params:
     """Pair-potential parameters of one evaluation."""
 
-    def __init__(self, cutoff, switch_width=1.0, dsf_alpha=0.2, sc_alpha=0.5, schedule=BEUTLER):
+    def __init__(self, cutoff, switch_width=1.0, dsf_alpha=0.2, sc_alpha=0.5, schedule=BEUTLER, ewald=False):
         self.cutoff = float(cutoff)
         self.switch_width = float(switch_width)
-        self.dsf_alpha = float(dsf_alpha)
+        self.dsf_alpha = float(dsf_alpha)   # the Ewald splitting parameter when ewald is set
         self.sc_alpha = float(sc_alpha)
         self.schedule = int(schedule)
+        self.ewald = bool(ewald)            # real-space Ewald erfc(a r)/r in place of D(r)
+
+    @property
+    def code(self):
+        """The schedule argument of the C entry points (bit 2: Ewald real space)."""
+        return self.schedule | (EWALD_REAL if self.ewald else 0)
 
     @classmethod
     def of(cls, workload, schedule=BEUTLER):
@@ -107,7 +117,7 @@ def evaluate(positions, types, is_solute, exclusions, box, sigma, epsilon, charg
     absterms = np.zeros(NTERMS)
     rc = lib.oracle_eval(n, _ptr(pos), _ptr(t), _ptr(s), ex.shape[0], _ptr(ex), _ptr(bx), sg.shape[0], _ptr(sg),
                          _ptr(ep), _ptr(ch), params.cutoff, params.switch_width, params.dsf_alpha, params.sc_alpha,
-                         params.schedule, float(lam), _ptr(terms), _ptr(f), _ptr(g), _ptr(npairs), _ptr(absterms),
+                         params.code, float(lam), _ptr(terms), _ptr(f), _ptr(g), _ptr(npairs), _ptr(absterms),
                          int(n_threads))
     if rc != 0:
         raise ValueError("oracle_eval rejected its input (code %d)" % rc)
@@ -153,7 +163,7 @@ def atom_energy(a, system, ff, params: Params, lam, positions=None):
     sg, ep, ch = _c(ff.sigma, np.float64), _c(ff.epsilon, np.float64), _c(ff.charge, np.float64)
     return lib.oracle_atom_energy(int(a), pos.shape[0], _ptr(pos), _ptr(t), _ptr(s), ex.shape[0], _ptr(ex),
                                   _ptr(bx), sg.shape[0], _ptr(sg), _ptr(ep), _ptr(ch), params.cutoff,
-                                  params.switch_width, params.dsf_alpha, params.sc_alpha, params.schedule,
+                                  params.switch_width, params.dsf_alpha, params.sc_alpha, params.code,
                                   float(lam))
 
 
@@ -172,7 +182,7 @@ def atoms_terms(sel, system, ff, params: Params, lam, positions=None, n_threads=
     f, e, dl, npair = np.zeros((S, 3)), np.zeros(S), np.zeros(S), np.zeros(S, np.int64)
     rc = lib.oracle_atoms_terms(S, _ptr(sl), pos.shape[0], _ptr(pos), _ptr(t), _ptr(s), ex.shape[0], _ptr(ex),
                                 _ptr(bx), sg.shape[0], _ptr(sg), _ptr(ep), _ptr(ch), params.cutoff,
-                                params.switch_width, params.dsf_alpha, params.sc_alpha, params.schedule, float(lam),
+                                params.switch_width, params.dsf_alpha, params.sc_alpha, params.code, float(lam),
                                 _ptr(f), _ptr(e), _ptr(dl), _ptr(npair), int(n_threads))
     if rc != 0:
         raise ValueError("oracle_atoms_terms rejected its input (code %d)" % rc)
@@ -184,7 +194,7 @@ def pair_probe(r, sig, eps, qq, alchemical, params: Params, lam):
     lib = _load()
     out = np.zeros(6)
     lib.oracle_pair_probe(float(r), float(sig), float(eps), float(qq), int(bool(alchemical)), params.cutoff,
-                          params.switch_width, params.dsf_alpha, params.sc_alpha, params.schedule, float(lam),
+                          params.switch_width, params.dsf_alpha, params.sc_alpha, params.code, float(lam),
                           _ptr(out))
     return out
 
@@ -210,4 +220,11 @@ def switch(r, rc, width):
 def dsf(r, rc, alpha):
     out = np.zeros(2)
     _load().oracle_dsf(float(r), float(rc), float(alpha), _ptr(out))
+    return out
+
+
+def ewald_real(r, alpha):
+    """erfc(alpha r)/r and its r derivative (the real-space Ewald kernel)."""
+    out = np.zeros(2)
+    _load().oracle_ewald_real(float(r), float(alpha), _ptr(out))
     return out

@@ -25,7 +25,11 @@
  *   D(r)     = damped shifted-force Coulomb kernel
  *              erfc(a r)/r - erfc(a r_c)/r_c
  *              + [erfc(a r_c)/r_c^2 + 2a/sqrt(pi) exp(-a^2 r_c^2)/r_c] (r - r_c),
- *              which vanishes with its first derivative at r_c.
+ *              which vanishes with its first derivative at r_c; with the
+ *              Ewald flag (OR_ELEC_EWALD) D(r) = erfc(a r)/r instead, the
+ *              real-space part of an Ewald sum (long-range electrostatics
+ *              by PME, Simulation Details section; oracle/pme.py adds the
+ *              reciprocal, self and exclusion parts).
  *   plain    u = LJ(r) S(r) + k_e q_i q_j D(r)
  *   Beutler  u = lv 4 eps (x^2 - x) S(r) + le k_e q_i q_j D(r),
  *              x = 1/(alpha_sc (1 - lv) + (r/sig)^6),
@@ -68,7 +72,18 @@ enum { SCHED_BEUTLER = 0, SCHED_LBF = 1 };
 typedef struct {
   double cutoff, switch_width, dsf_alpha, sc_alpha;
   int schedule;
+  int ewald;  /* 1: Ewald real space erfc(a r)/r in place of D(r) */
 } or_params;
+
+/* The schedule argument of the entry points carries the electrostatics in
+ * bit 2: clear = damped shifted force D(r); OR_ELEC_EWALD = the real-space
+ * part of an Ewald sum, erfc(a r)/r truncated at r_c without shift (the
+ * reciprocal part, self and exclusion terms are computed elsewhere). */
+#define OR_ELEC_EWALD 4
+static or_params make_params(double cutoff, double switch_width, double alpha, double sc_alpha, int code) {
+  or_params p = {cutoff, switch_width, alpha, sc_alpha, code & 3, (code & OR_ELEC_EWALD) ? 1 : 0};
+  return p;
+}
 
 /* ---------------------------------------------------------------- helpers */
 
@@ -130,6 +145,13 @@ void oracle_dsf(double r, double rc, double a, double out[2]) {
   out[1] = -erfc(a * r) / (r * r) - a * two_over_sqrt_pi * exp(-a * a * r * r) / r + slope;
 }
 
+/* Ewald real-space kernel erfc(a r)/r and its r derivative */
+void oracle_ewald_real(double r, double a, double out[2]) {
+  const double two_over_sqrt_pi = 2.0 / sqrt(M_PI);
+  out[0] = erfc(a * r) / r;
+  out[1] = -erfc(a * r) / (r * r) - a * two_over_sqrt_pi * exp(-a * a * r * r) / r;
+}
+
 /* Lennard-Jones 4 eps [(s/r)^12 - (s/r)^6] and its r, sigma, eps derivatives */
 static void lj(double r, double sig, double eps, double *u, double *du_dr, double *du_ds, double *du_de) {
   double sr6 = pow(sig / r, 6), sr12 = sr6 * sr6;
@@ -176,7 +198,8 @@ static void eval_pair(double r, double sig, double eps, double qq, int alchemica
   memset(o, 0, sizeof(*o));
   double sw[2], dsf[2];
   oracle_switch(r, p->cutoff, p->switch_width, sw);
-  oracle_dsf(r, p->cutoff, p->dsf_alpha, dsf);
+  if (p->ewald) oracle_ewald_real(r, p->dsf_alpha, dsf);
+  else oracle_dsf(r, p->cutoff, p->dsf_alpha, dsf);
   double ulj, dlj_dr, dlj_ds, dlj_de;
   lj(r, sig, eps, &ulj, &dlj_dr, &dlj_ds, &dlj_de);
   /* switched LJ and Coulomb pieces shared by plain pairs and LBF's U_A */
@@ -288,16 +311,18 @@ int oracle_eval(int n, const double *pos, const int32_t *type, const uint8_t *is
                 const double *charge, double cutoff, double switch_width, double dsf_alpha, double sc_alpha,
                 int schedule, double lambda, double *terms, double *forces, double *pgrad, int64_t *n_pairs,
                 double *abs_terms, int n_threads) {
-  if (n < 0 || cutoff <= 0 || (schedule != SCHED_BEUTLER && schedule != SCHED_LBF)) return -1;
+  if (n < 0 || cutoff <= 0 || ((schedule & 3) != SCHED_BEUTLER && (schedule & 3) != SCHED_LBF) ||
+      (schedule & ~(3 | OR_ELEC_EWALD)) != 0)
+    return -1;
   for (int d = 0; d < 3; ++d)
     if (!(box[d] >= 2.0 * cutoff)) return -4;
   for (int i = 0; i < n; ++i)
     if (type[i] < 0 || type[i] >= n_types) return -5;
   excl_index ix;
   if (excl_build(n, n_excl, excl, &ix) != 0) return -6;
-  or_params p = {cutoff, switch_width, dsf_alpha, sc_alpha, schedule};
+  const or_params p = make_params(cutoff, switch_width, dsf_alpha, sc_alpha, schedule);
   lam_state ls;
-  lam_state_init(lambda, schedule, &ls);
+  lam_state_init(lambda, p.schedule, &ls);
 
   double *w = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
   for (int i = 0; i < n; ++i) wrap3(pos + 3 * i, box, w + 3 * i);
@@ -474,9 +499,9 @@ double oracle_atom_energy(int a, int n, const double *pos, const int32_t *type, 
                           const double *epsilon, const double *charge, double cutoff, double switch_width,
                           double dsf_alpha, double sc_alpha, int schedule, double lambda) {
   (void)n_types;
-  or_params p = {cutoff, switch_width, dsf_alpha, sc_alpha, schedule};
+  const or_params p = make_params(cutoff, switch_width, dsf_alpha, sc_alpha, schedule);
   lam_state ls;
-  lam_state_init(lambda, schedule, &ls);
+  lam_state_init(lambda, p.schedule, &ls);
   double wa[3];
   wrap3(pos + 3 * a, box, wa);
   ksum e = {0, 0};
@@ -515,7 +540,9 @@ int oracle_atoms_terms(int n_sel, const int32_t *sel, int n, const double *pos, 
                        const double *sigma, const double *epsilon, const double *charge, double cutoff,
                        double switch_width, double dsf_alpha, double sc_alpha, int schedule, double lambda,
                        double *force, double *energy, double *dudl, int64_t *n_pairs, int n_threads) {
-  if (n < 0 || cutoff <= 0 || (schedule != SCHED_BEUTLER && schedule != SCHED_LBF)) return -1;
+  if (n < 0 || cutoff <= 0 || ((schedule & 3) != SCHED_BEUTLER && (schedule & 3) != SCHED_LBF) ||
+      (schedule & ~(3 | OR_ELEC_EWALD)) != 0)
+    return -1;
   for (int d = 0; d < 3; ++d)
     if (!(box[d] >= 2.0 * cutoff)) return -4;
   for (int i = 0; i < n; ++i)
@@ -524,9 +551,9 @@ int oracle_atoms_terms(int n_sel, const int32_t *sel, int n, const double *pos, 
     if (sel[s] < 0 || sel[s] >= n) return -7;
   excl_index ix;
   if (excl_build(n, n_excl, excl, &ix) != 0) return -6;
-  or_params p = {cutoff, switch_width, dsf_alpha, sc_alpha, schedule};
+  const or_params p = make_params(cutoff, switch_width, dsf_alpha, sc_alpha, schedule);
   lam_state ls;
-  lam_state_init(lambda, schedule, &ls);
+  lam_state_init(lambda, p.schedule, &ls);
   double *w = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
   for (int i = 0; i < n; ++i) wrap3(pos + 3 * i, box, w + 3 * i);
   const double rc2 = cutoff * cutoff;
@@ -576,9 +603,9 @@ int oracle_atoms_terms(int n_sel, const int32_t *sel, int n, const double *pos, 
 void oracle_pair_probe(double r, double sig, double eps, double qq, int alchemical, double cutoff,
                        double switch_width, double dsf_alpha, double sc_alpha, int schedule, double lambda,
                        double *out) {
-  or_params p = {cutoff, switch_width, dsf_alpha, sc_alpha, schedule};
+  const or_params p = make_params(cutoff, switch_width, dsf_alpha, sc_alpha, schedule);
   lam_state ls;
-  lam_state_init(lambda, schedule, &ls);
+  lam_state_init(lambda, p.schedule, &ls);
   pair_out o;
   eval_pair(r, sig, eps, qq, alchemical, &p, &ls, &o);
   out[0] = alchemical ? o.ss_vdw + o.ss_elec : o.u_plain;
