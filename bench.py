@@ -250,6 +250,27 @@ def aux_paths(torch, w, traj, lams, W, K):
             "device_flags": flags}
 
 
+def pme_path(torch, w, traj, lams, W, K, dsf_ms):
+    """The same walk with Ewald electrostatics by smooth PME (FP32 pairs):
+    splitting parameter from erfc(a r_c) = 5e-4 (a r_c = 2.46), 1 A grid
+    spacing, order 5."""
+    from paper_2608_12691_amd import alchnb
+    from scipy.special import erfcinv
+    alpha = float(erfcinv(5e-4)) / w.cutoff
+    ctx = alchnb.Context(w.ff, w.systems, w.cutoff, w.skin, w.switch_width, alpha, w.sc_alpha,
+                         precision=alchnb.FP32_FIXED, electrostatics=alchnb.ELEC_PME, pme_order=5, pme_spacing=1.0)
+    ctx.compute_checked(traj[0].clone(), lams[0].clone(), flags=alchnb.FORCE_REBUILD)
+    elapsed, tile_ms, out, rebuilds, _, _ = run_path(ctx, traj, lams, W, K, torch, False)
+    n_pairs = count_pairs(ctx, traj, lams, W, K, torch)
+    flags = ctx.get_flags()
+    grid = ctx.pme_grid(0)
+    ctx.close()
+    ms = 1e3 * elapsed / K
+    return {"value": n_pairs / elapsed, "ms_per_step": ms, "steps": K, "pme_us_per_step": 1e3 * (ms - dsf_ms),
+            "tile_us": tile_ms * 1e3 if tile_ms else None, "grid": list(grid), "order": 5, "alpha": alpha,
+            "spacing": 1.0, "rebuilds": rebuilds, "device_flags": flags}
+
+
 def rebuild_cost(ctx, traj, lams, torch, reps=10):
     """Extra time of a call that rebuilds the list: forced rebuilds against
     plain calls at the same positions (HIP events on the bound stream)."""
@@ -313,6 +334,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200)
+    ap.add_argument("--no-pme", action="store_true")
     ap.add_argument("--no-aux", action="store_true")
     ap.add_argument("--aux-steps", type=int, default=300)
     ap.add_argument("--rebuild-calls", type=int, default=1000, help="walk length for the calls-per-rebuild figure")
@@ -429,6 +451,8 @@ def main():
     line["device_flags"] = {"fp32": r32["flags"], "fp64": res.get(alchnb.FP64, {}).get("flags")}
     if not args.no_batched:
         optional(line, "hrex16", lambda: batched_vs_single(torch, args.batched_steps, 20, args.mode == "graph"))
+    if not args.no_pme:
+        optional(line, "pme", lambda: pme_path(torch, w, traj, lams, W, K, line["ms_per_step"]))
     if not args.no_aux:
         optional(line, "aux", lambda: aux_paths(torch, w, traj, lams, min(W, 20), min(K, args.aux_steps)))
     if not args.no_cpu_baseline:

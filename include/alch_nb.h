@@ -127,7 +127,22 @@ typedef struct {
   int32_t precision;          /* ALCH_NB_FP32_FIXED | ALCH_NB_FP64 */
   int32_t variant;            /* launch variant index, -1 = default (see alch_nb_autotune) */
   double list_capacity_factor;/* scales the neighbour-list capacity estimate; <= 0 means 1 */
+  /* Long-range electrostatics (appended; zero-initialised callers get DSF).
+   * ALCH_NB_ELEC_PME: Ewald electrostatics by smooth particle-mesh Ewald,
+   * as the paper's simulations use (Simulation Details): dsf_alpha is then
+   * the Ewald splitting parameter a > 0, D(r) becomes erfc(a r)/r truncated
+   * at the cutoff, and the reciprocal-space, self, excluded-pair and
+   * neutralising-background parts are added per box, the solute-solvent
+   * part of each scaled like the solute-solvent Coulomb pairs (see
+   * alch_nb_compute). */
+  int32_t electrostatics;     /* ALCH_NB_ELEC_DSF (0) | ALCH_NB_ELEC_PME */
+  int32_t pme_order;          /* B-spline interpolation order, 4..6 (PME) */
+  double pme_spacing;         /* largest grid spacing, Angstrom (PME): each box edge L gets the
+                                 smallest n >= max(L / pme_spacing, 2 pme_order) of the form
+                                 2^a 3^b 5^c; n > 512 gives ALCH_NB_E_UNSUPPORTED */
 } alch_nb_params;
+
+enum { ALCH_NB_ELEC_DSF = 0, ALCH_NB_ELEC_PME = 1 };  /* electrostatics */
 
 /* Outputs of alch_nb_compute().  Device pointers; any may be NULL. */
 typedef struct {
@@ -165,6 +180,10 @@ typedef struct {
  * planning; no HIP call).  *out receives the context or NULL on error. */
 alch_nb_status alch_nb_create(const alch_nb_params *params, const alch_nb_system *systems, int32_t n_systems,
                               alch_nb_ctx **out);
+
+/* PME grid of box k (ALCH_NB_ELEC_PME): dims[3] = grid points along x, y, z.
+ * ALCH_NB_E_UNSUPPORTED for a DSF context. */
+alch_nb_status alch_nb_pme_grid(const alch_nb_ctx *ctx, int32_t k, int32_t dims[3]);
 
 /* Bytes of device workspace the context needs. */
 alch_nb_status alch_nb_workspace_size(const alch_nb_ctx *ctx, size_t *bytes);
@@ -215,7 +234,19 @@ alch_nb_status alch_nb_build_list(alch_nb_ctx *ctx, const double *d_pos);
  * device when an atom moved more than skin/2 since the last build (always
  * when skin = 0); ALCH_NB_FORCE_REBUILD rebuilds unconditionally.  Outputs
  * are written in full (forces in atom order; terms per box as listed under
- * ALCH_NB_T_*); any output pointer may be NULL. */
+ * ALCH_NB_T_*); any output pointer may be NULL.
+ * With ALCH_NB_ELEC_PME the Coulomb energy is an Ewald sum (long-range
+ * electrostatics by PME: Simulation Details; smooth PME of Essmann et al.
+ * 1995): the short-range pairs use erfc(a r)/r, and per box the smooth-PME
+ * reciprocal energy of two charge grids (solute S, solvent W; order-n
+ * cardinal B-splines, FP64 complex FFTs, 64-bit fixed-point charge spreading
+ * so that results stay bit-identical), the self part -k_e a/sqrt(pi) sum
+ * q^2, the excluded pairs' -k_e q q erf(a r)/r and the background part
+ * -k_e pi Q^2/(2 V a^2) are split into S-S, W-W and S-W parts.  S-S and
+ * W-W join E_solu_solu and E_solv_solv; the S-W part X is scaled like the
+ * solute-solvent Coulomb pairs (Beutler: le X in E_ss_elec, dle/dlambda X
+ * in dU/dlambda; LBF: X joins U_A, hA X E_ss_elec, hA' X dU/dlambda), and
+ * the forces are those of that energy. */
 alch_nb_status alch_nb_compute(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda, uint32_t flags,
                                const alch_nb_out *out);
 
@@ -230,8 +261,9 @@ alch_nb_status alch_nb_compute(alch_nb_ctx *ctx, const double *d_pos, const doub
  * inputs of that call.  The parameter gradients are per-atom 64-bit
  * fixed-point sums (the forces' scale; a value beyond 2^62 units raises
  * ALCH_NB_FLAG_FIXED_OVERFLOW) added per type in a fixed order, so repeated
- * calls give identical results.  They need n_types <= 256
- * (ALCH_NB_E_UNSUPPORTED otherwise). */
+ * calls give identical results.  They need n_types <= 256 and DSF
+ * electrostatics (ALCH_NB_E_UNSUPPORTED otherwise; with PME the position
+ * and lambda gradients are available, the per-type ones are not). */
 alch_nb_status alch_nb_backward(alch_nb_ctx *ctx, const double *d_pos, const double *d_lambda,
                                 const double *d_grad_energy, const alch_nb_grad *grad);
 

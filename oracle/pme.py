@@ -277,8 +277,22 @@ def evaluate(positions, types, is_solute, exclusions, box, sigma, epsilon, charg
     t[7] += dc * X
     t[8] += e_ww + e_ss + c * X
     t[9] += dc * X
+    # magnitudes of what each slot sums (error scales): the pair oracle's sums of |u| plus the
+    # magnitudes of the reciprocal and correction parts
+    ab = r["abs_terms"].copy()
+    p_ww = abs(rec["e_ww"]) + abs(cor["e_ww"])
+    p_ss = abs(rec["e_ss"]) + abs(cor["e_ss"])
+    p_x = abs(rec["e_sw"]) + abs(cor["e_sw"])
+    ab[0] += p_ww
+    ab[1] += p_ss
+    ab[3] += abs(c) * p_x
+    if params.schedule == O.LBF:
+        ab[4] += p_x
+    ab[7] += abs(dc) * p_x
+    ab[8] += p_ww + p_ss + abs(c) * p_x
+    ab[9] += abs(dc) * p_x
     return dict(terms=t, forces=r["forces"] + rec["forces"] + cor["forces"], n_pairs=r["n_pairs"],
-                recip=rec, corr=cor, cross=X)
+                recip=rec, corr=cor, cross=X, abs_terms=ab)
 
 
 def evaluate_system(system, ff, params, lam, grid, order, **kw):

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("ALCHNB_LIB") or os.path.join(_HERE, "libalchnb.so")
 
 BEUTLER_DSF, LBF_DSF = 0, 1
 FP32_FIXED, FP64 = 0, 1
+ELEC_DSF, ELEC_PME = 0, 1
 AUTO_REBUILD, FORCE_REBUILD = 1, 2
 FLAG_FIXED_OVERFLOW, FLAG_SKIN_EXCEEDED, FLAG_NONFINITE, FLAG_LAMBDA_RANGE, FLAG_CAPACITY = 1, 2, 4, 8, 16
 FLAG_BARRIER_TIMEOUT, FLAG_BAD_INDEX, FLAG_LD_CAPACITY = 32, 64, 128
@@ -31,7 +32,7 @@ OPES_HEADER = 16
 STATUS = {0: "ok", 1: "invalid argument", 2: "box too small", 3: "unsupported", 4: "capacity", 5: "hip error",
           6: "not bound", 7: "no device", 8: "workspace exceeds the static scratch"}
 
-EXPORTED = ["alch_nb_create", "alch_nb_workspace_size", "alch_nb_bind", "alch_nb_bind_static", "alch_nb_build_list", "alch_nb_compute",
+EXPORTED = ["alch_nb_create", "alch_nb_pme_grid", "alch_nb_workspace_size", "alch_nb_bind", "alch_nb_bind_static", "alch_nb_build_list", "alch_nb_compute",
             "alch_nb_backward", "alch_nb_dihedrals", "alch_nb_opes_update", "alch_nb_opes_layout", "alch_nb_opes_init", "alch_nb_opes_state_size",
             "alch_nb_ld_state_size", "alch_nb_ld_layout", "alch_nb_ld_init", "alch_nb_ld_step",
             "alch_nb_ld_free_energy", "alch_nb_hrex_init", "alch_nb_hrex_exchange", "alch_nb_capture_begin",
@@ -59,7 +60,8 @@ class Params_t(ctypes.Structure):
                 ("charge", ctypes.c_void_p), ("cutoff", ctypes.c_double), ("skin", ctypes.c_double),
                 ("switch_width", ctypes.c_double), ("dsf_alpha", ctypes.c_double), ("sc_alpha", ctypes.c_double),
                 ("schedule", ctypes.c_int32), ("precision", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("list_capacity_factor", ctypes.c_double)]
+                ("list_capacity_factor", ctypes.c_double), ("electrostatics", ctypes.c_int32),
+                ("pme_order", ctypes.c_int32), ("pme_spacing", ctypes.c_double)]
 
 
 class Out_t(ctypes.Structure):
@@ -107,6 +109,7 @@ def load():
         sig = {
             "alch_nb_create": ([P, P, I32, P], I32),
             "alch_nb_workspace_size": ([P, P], I32),
+            "alch_nb_pme_grid": ([P, I32, P], I32),
             "alch_nb_bind": ([P, P, ctypes.c_size_t, P], I32),
             "alch_nb_bind_static": ([P, P], I32),
             "alch_nb_build_list": ([P, P], I32),
@@ -165,7 +168,7 @@ class Context:
 
     def __init__(self, ff, systems: Sequence, cutoff, skin, switch_width=1.0, dsf_alpha=0.2, sc_alpha=0.5,
                  schedule=BEUTLER_DSF, precision=FP32_FIXED, variant=-1, capacity_factor=1.0, device=None,
-                 auto_capacity=True, static_scratch=False):
+                 auto_capacity=True, static_scratch=False, electrostatics=ELEC_DSF, pme_order=5, pme_spacing=1.0):
         import torch
         self.torch = torch
         self.lib = load()
@@ -194,7 +197,9 @@ class Context:
         self._chg = np.ascontiguousarray(ff.charge, np.float64)
         self._p = Params_t(self.n_types, self._sig.ctypes.data, self._eps.ctypes.data, self._chg.ctypes.data,
                            float(cutoff), float(skin), float(switch_width), float(dsf_alpha), float(sc_alpha),
-                           self.schedule, self.precision, int(variant), float(capacity_factor))
+                           self.schedule, self.precision, int(variant), float(capacity_factor),
+                           int(electrostatics), int(pme_order), float(pme_spacing))
+        self.electrostatics = int(electrostatics)
         self.ctx = None
         # bumped by every call that rewrites the forward state (list, slots,
         # force sums): a backward needs the state of its own forward
@@ -219,6 +224,12 @@ class Context:
         nb = ctypes.c_size_t()
         self._check("alch_nb_workspace_size", self.lib.alch_nb_workspace_size(self.ctx, ctypes.byref(nb)))
         self.workspace_bytes = nb.value
+
+    def pme_grid(self, k=0):
+        """PME grid points (x, y, z) of box k."""
+        dims = (ctypes.c_int32 * 3)()
+        self._check("alch_nb_pme_grid", self.lib.alch_nb_pme_grid(self.ctx, int(k), dims))
+        return tuple(int(v) for v in dims)
 
     def _bind(self):
         torch = self.torch

@@ -20,7 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libalchnb.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "alchnb")
-SOURCES = ["alch_nb.cpp", "list_kernels.hip", "tile_kernels.hip", "aux_kernels.hip", "ldyn_kernels.hip", "hrex_kernels.hip", "noalloc.hip"]
+SOURCES = ["alch_nb.cpp", "list_kernels.hip", "tile_kernels.hip", "aux_kernels.hip", "ldyn_kernels.hip",
+           "hrex_kernels.hip", "noalloc.hip", "pme_kernels.hip"]
 HEADERS = ["anb_internal.h", "anb_kernels.h", "erfc_coeffs.h", "lane_ops.h", "pair_math.h"]
 ARCH = "gfx950"
 

@@ -96,6 +96,15 @@ struct alch_nb_ctx {
   double tuned_ms = 0;  // tile time of the variant chosen by the autotuner
   int ld_ncv = -1;       // auxiliary variables of the last lambda-dynamics state initialised (-1: none)
   bool capturing = false;  // between alch_nb_capture_begin and _end (no timing events then)
+  // PME (electrostatics ALCH_NB_ELEC_PME)
+  bool pme = false;
+  std::vector<PmeBox> pme_box;
+  std::vector<double2> pme_roots;
+  std::vector<double> pme_bmod;
+  long long pme_points = 0;
+  int pme_lines[3] = {0, 0, 0};
+  int pme_tab = 0;  // entries of the axis tables
+  double pme_qscale = 0;  // fixed-point units per e of the charge grids
 };
 
 static alch_nb_status hip_fail(alch_nb_ctx* c, hipError_t e) {
@@ -200,6 +209,30 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->dsf32 = cv.take<float4>(base, kDsfEntries);
   d->tp64 = cv.take<double4>(base, (size_t)ctx->T * ctx->T);
   d->pot64 = cv.take<double>(base, kPot64Words);
+  if (ctx->pme) {
+    d->pme_box = cv.take<PmeBox>(base, K);
+    d->pme_grid = cv.take<double2>(base, (size_t)ctx->pme_points);
+    d->pme_q = cv.take<unsigned long long>(base, 2 * (size_t)ctx->pme_points);
+    d->pme_roots = cv.take<double2>(base, ctx->pme_tab);
+    d->pme_bmod = cv.take<double>(base, ctx->pme_tab);
+    d->pme_part = cv.take<double>(base, K * kPmeParts * PME_NPART);
+    d->pme_points = ctx->pme_points;
+    for (int a = 0; a < 3; ++a) d->pme_lines[a] = ctx->pme_lines[a];
+    d->pme_order = ctx->p.pme_order;
+    d->pme_alpha = ctx->p.dsf_alpha;
+    d->pme_qscale = ctx->pme_qscale;
+  } else {
+    d->pme_box = nullptr;
+    d->pme_grid = nullptr;
+    d->pme_q = nullptr;
+    d->pme_roots = nullptr;
+    d->pme_bmod = nullptr;
+    d->pme_part = nullptr;
+    d->pme_points = 0;
+    d->pme_order = 0;
+    d->pme_alpha = 0.0;
+    d->pme_qscale = 0.0;
+  }
   ctx->export_counter = cv.take<unsigned long long>(base, 1);
   ctx->ws_bytes = cv.off + 256;
 }
@@ -213,6 +246,44 @@ static std::string tune_key(const alch_nb_ctx* ctx);
 static int tune_cache_lookup(const std::string& key);
 
 extern "C" {
+
+// PME grid points along an edge L: the smallest n >= max(L / spacing, 2
+// order) whose prime factors are 2, 3 and 5 (-1 beyond kPmeMaxN).
+static int pme_size(double L, double spacing, int order) {
+  int n = std::max((int)std::ceil(L / spacing - 1e-9), 2 * order);
+  for (; n <= kPmeMaxN; ++n) {
+    int m = n;
+    for (int f : {2, 3, 5})
+      while (m % f == 0) m /= f;
+    if (m == 1) return n;
+  }
+  return -1;
+}
+
+// Cardinal B-spline M_n(u) (support (0, n)) by its recursion from the hat M_2.
+static double bspline_host(double u, int n) {
+  if (n == 2) return (u >= 0.0 && u <= 2.0) ? 1.0 - std::fabs(u - 1.0) : 0.0;
+  return (u * bspline_host(u, n - 1) + (n - u) * bspline_host(u - 1.0, n - 1)) / (n - 1);
+}
+
+// |b(m)|^2 = 1/|sum_{k<n-1} M_n(k+1) exp(2 pi i m k/K)|^2, m < K; a vanishing
+// denominator (odd order, m = K/2) takes the mean of its neighbours' |.|^2.
+static void bspline_moduli(int K, int n, double* out) {
+  std::vector<double> d2(K);
+  for (int m = 0; m < K; ++m) {
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < n - 1; ++k) {
+      const double M = bspline_host(k + 1.0, n);
+      const double ph = 2.0 * M_PI * (double)((long long)m * k % K) / K;
+      re += M * std::cos(ph);
+      im += M * std::sin(ph);
+    }
+    d2[m] = re * re + im * im;
+  }
+  for (int m = 0; m < K; ++m)
+    if (d2[m] < 1e-10) d2[m] = 0.5 * (d2[(m + K - 1) % K] + d2[(m + 1) % K]);
+  for (int m = 0; m < K; ++m) out[m] = 1.0 / d2[m];
+}
 
 const char* alch_nb_strerror(alch_nb_status s) {
   switch (s) {
@@ -264,6 +335,10 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
     return ALCH_NB_E_INVALID_ARG;
   if (p.schedule != ALCH_NB_BEUTLER_DSF && p.schedule != ALCH_NB_LBF_DSF) return ALCH_NB_E_INVALID_ARG;
   if (p.precision != ALCH_NB_FP32_FIXED && p.precision != ALCH_NB_FP64) return ALCH_NB_E_INVALID_ARG;
+  if (p.electrostatics != ALCH_NB_ELEC_DSF && p.electrostatics != ALCH_NB_ELEC_PME) return ALCH_NB_E_INVALID_ARG;
+  if (p.electrostatics == ALCH_NB_ELEC_PME &&
+      (p.pme_order < kPmeMinOrder || p.pme_order > kPmeMaxOrder || !(p.pme_spacing > 0) || !(p.dsf_alpha > 0)))
+    return ALCH_NB_E_INVALID_ARG;
   if (p.variant < -1 || p.variant >= kNumVariants) return ALCH_NB_E_INVALID_ARG;
   for (int t = 0; t < p.n_types; ++t)
     if (!(p.sigma[t] > 0) || !(p.epsilon[t] >= 0) || !std::isfinite(p.charge[t])) return ALCH_NB_E_INVALID_ARG;
@@ -448,6 +523,57 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
   ctx->ent_cap = (int)ent_cap;
   ctx->unit_cap = ctx->ent_cap + ctx->sc_cap + 1;  // a unit holds at least one entry
 
+  // PME grids, root tables and B-spline moduli per box and axis
+  if (p.electrostatics == ALCH_NB_ELEC_PME) {
+    ctx->pme = true;
+    long long pts = 0;
+    int tab = 0, lines[3] = {0, 0, 0};
+    for (int k = 0; k < n_systems; ++k) {
+      PmeBox B{};
+      for (int a = 0; a < 3; ++a) {
+        B.n[a] = pme_size(sys[k].box[a], p.pme_spacing, p.pme_order);
+        B.L[a] = sys[k].box[a];
+        if (B.n[a] < 0) {
+          delete ctx;
+          return ALCH_NB_E_UNSUPPORTED;
+        }
+      }
+      B.off = pts;
+      pts += (long long)B.n[0] * B.n[1] * B.n[2];
+      const int per_axis[3] = {B.n[1] * B.n[2], B.n[0] * B.n[2], B.n[0] * B.n[1]};
+      for (int a = 0; a < 3; ++a) {
+        B.lines[a] = lines[a];
+        lines[a] += per_axis[a];
+        B.tab[a] = tab;
+        tab += B.n[a];
+        for (int i = 0; i < B.n[a]; ++i) {
+          const double ph = 2.0 * M_PI * i / B.n[a];
+          ctx->pme_roots.push_back(make_double2(std::cos(ph), -std::sin(ph)));
+        }
+        const size_t b0 = ctx->pme_bmod.size();
+        ctx->pme_bmod.resize(b0 + B.n[a]);
+        bspline_moduli(B.n[a], p.pme_order, ctx->pme_bmod.data() + b0);
+      }
+      ctx->pme_box.push_back(B);
+    }
+    if (pts > (1LL << 31)) {
+      delete ctx;
+      return ALCH_NB_E_UNSUPPORTED;
+    }
+    ctx->pme_points = pts;
+    ctx->pme_tab = tab;
+    // charge-grid scale: a power of two that keeps the largest possible grid
+    // value (the box's sum of |q_i|) below 2^62 units, at most 2^52
+    double qmax = 1.0;
+    for (int k = 0; k < n_systems; ++k) {
+      double qs = 0.0;
+      for (int i = 0; i < sys[k].n_atoms; ++i) qs += std::fabs(p.charge[sys[k].type[i]]);
+      qmax = std::max(qmax, qs);
+    }
+    ctx->pme_qscale = std::exp2(std::min(52.0, std::floor(62.0 - std::log2(qmax))));
+    for (int a = 0; a < 3; ++a) ctx->pme_lines[a] = lines[a];
+  }
+
   // potential constants (FP64)
   PotConsts& pc = ctx->pc;
   pc.rc = p.cutoff;
@@ -459,6 +585,10 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
   pc.A = ec / p.cutoff;
   pc.c2a = 2.0 * p.dsf_alpha / std::sqrt(M_PI);
   pc.B = ec / (p.cutoff * p.cutoff) + pc.c2a * std::exp(-p.dsf_alpha * p.dsf_alpha * p.cutoff * p.cutoff) / p.cutoff;
+  if (ctx->pme) {  // Ewald real space: erfc(a r)/r with no shift
+    pc.A = 0.0;
+    pc.B = 0.0;
+  }
   pc.sc_alpha = p.sc_alpha;
   // intervals per unit of r: the largest power of two with rc * inv_h <= kDsfN,
   // so that r * inv_h and its fraction are exact in FP32
@@ -498,6 +628,13 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
     if (v >= 0) ctx->variant = v;
   }
   *out = ctx;
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_pme_grid(const alch_nb_ctx* ctx, int32_t k, int32_t dims[3]) {
+  if (!ctx || !dims || k < 0 || k >= ctx->K) return ALCH_NB_E_INVALID_ARG;
+  if (!ctx->pme) return ALCH_NB_E_UNSUPPORTED;
+  for (int a = 0; a < 3; ++a) dims[a] = ctx->pme_box[k].n[a];
   return ALCH_NB_OK;
 }
 
@@ -574,6 +711,11 @@ alch_nb_status anb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* stream
   double pw[kPot64Words];
   pot64_words(ctx->pc, pw);
   HIPCHK(up(d.pot64, pw, sizeof(pw)));
+  if (ctx->pme) {
+    HIPCHK(up(d.pme_box, ctx->pme_box.data(), sizeof(PmeBox) * ctx->pme_box.size()));
+    HIPCHK(up(d.pme_roots, ctx->pme_roots.data(), sizeof(double2) * ctx->pme_roots.size()));
+    HIPCHK(up(d.pme_bmod, ctx->pme_bmod.data(), sizeof(double) * ctx->pme_bmod.size()));
+  }
   HIPCHK(launch_init(d, st));
   // the host copies must outlive the asynchronous uploads
   HIPCHK(hipStreamSynchronize(st));
@@ -614,6 +756,7 @@ static alch_nb_status enqueue_compute(alch_nb_ctx* ctx, const double* pos, const
     HIPCHK(hipEventRecord(ctx->ev[2 * ctx->n_timed + 1], st));
     ctx->n_timed++;
   }
+  if (ctx->pme) HIPCHK(launch_pme(d, st, pos, p.schedule, p.precision));
   HIPCHK(launch_finalize(d, st, p.precision, p.schedule, out ? out->terms : nullptr, out ? out->forces : nullptr,
                          out ? out->dudl : nullptr, out ? reinterpret_cast<long long*>(out->n_pairs) : nullptr));
   return ALCH_NB_OK;
@@ -780,7 +923,7 @@ alch_nb_status alch_nb_backward(alch_nb_ctx* ctx, const double* d_pos, const dou
   if (grad->d_pos || grad->d_lambda)
     HIPCHK(launch_backward_finish(d, ctx->stream, ctx->p.precision, d_grad_energy, grad->d_pos, grad->d_lambda));
   if (grad->d_sigma || grad->d_sqrt_epsilon || grad->d_charge || grad->d_epsilon) {
-    if (ctx->T > kMaxTypes) return ALCH_NB_E_UNSUPPORTED;
+    if (ctx->T > kMaxTypes || ctx->pme) return ALCH_NB_E_UNSUPPORTED;
     HIPCHK(launch_param_grads(d, ctx->stream, ctx->pc, ctx->p.precision, ctx->p.schedule, d_grad_energy,
                               grad->d_sigma, grad->d_sqrt_epsilon, grad->d_charge, grad->d_epsilon));
   }

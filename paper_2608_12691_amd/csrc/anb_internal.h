@@ -76,6 +76,37 @@ __host__ __device__ inline uint32_t ent_pack(uint32_t imask, uint32_t kind, uint
   return imask | (kind << 8) | (shift << 16);
 }
 
+// Smooth particle-mesh Ewald (electrostatics ALCH_NB_ELEC_PME).  Per box
+// one complex FP64 grid, z fastest, holding the solute charge grid in the
+// real part and the solvent grid in the imaginary part (after the forward
+// transform their spectra mixed; after the convolution and the inverse
+// transform the two potential grids G_S, G_W), and two int64 fixed-point
+// spreading grids (S, W) that the first FFT pass reads and clears.  Per box
+// and axis an FFT root table exp(-2 pi i k/n) and the B-spline moduli
+// |b(m)|^2.  Partial sums per box: kPmeParts blocks of the convolution and
+// of the gather each write PME_NPART values (their own slots).  The charge
+// grids count pme_qscale units per e, a power of two with
+// pme_qscale * max_box sum |q_i| <= 2^62 (a grid value never exceeds the
+// box's sum of |q_i|: the spline weights of an atom are at most 1), at most
+// 2^52.
+constexpr int kPmeMaxN = 512;       // grid points per edge at most
+constexpr int kPmeMinOrder = 4, kPmeMaxOrder = 6;
+constexpr int kPmeParts = 32;
+enum {
+  PME_E_SS = 0, PME_E_WW = 1, PME_E_SW = 2,   // reciprocal parts (convolution)
+  PME_C_SS = 3, PME_C_WW = 4, PME_C_SW = 5,   // self and excluded-pair parts (gather)
+  PME_Q_S = 6, PME_Q_W = 7,                   // group charges (gather; background part)
+  PME_NPART = 8
+};
+struct PmeBox {
+  int n[3];          // grid points per axis
+  int tab[3];        // offsets of the axis tables in pme_roots and pme_bmod
+  int lines[3];      // first line of this box in the pass along each axis (prefix over boxes)
+  int pad_;
+  long long off;     // first grid point of the box
+  double L[3];       // box edges
+};
+
 // Device view of the workspace.
 struct Dev {
   int n_atoms, n_reps, n_grids, n_cols, sc_cap, ent_cap, unit_cap, n_types;
@@ -154,6 +185,18 @@ struct Dev {
   const float4* dsf32;       // [kDsfEntries] FP32 DSF pieces (erfc, then the Gaussian term, per interval)
   const double4* tp64;       // [T*T]
   const double* pot64;       // [kPot64Words] FP64 potential constants of the solute units (see pot64_words)
+  // PME (pme_box == nullptr: DSF electrostatics)
+  const PmeBox* pme_box;     // [K]
+  double2* pme_grid;         // [pme_points]
+  unsigned long long* pme_q; // [2][pme_points] charge spreading grids S, W (fixed point)
+  const double2* pme_roots;  // per box and axis: exp(-2 pi i k/n), k < n
+  const double* pme_bmod;    // per box and axis: |b(m)|^2
+  double* pme_part;          // [K][kPmeParts][PME_NPART]
+  long long pme_points;      // grid points of all boxes
+  int pme_lines[3];          // lines of all boxes per axis
+  int pme_order;
+  double pme_alpha;          // Ewald splitting parameter
+  double pme_qscale;         // fixed-point units per e of the charge grids
 };
 
 // Replica exchange: boxes per context it handles, and the terms per box.

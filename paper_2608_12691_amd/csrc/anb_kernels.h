@@ -52,6 +52,9 @@ hipError_t launch_tile(const Dev& d, hipStream_t st, const PotConsts& pc, int pr
                        const TileShape& shape, const double* xin);
 hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int schedule, double* terms,
                            double* forces, double* dudl, long long* n_pairs);
+// Smooth-PME reciprocal space, self and excluded-pair parts of every box
+// (after the tile kernel, before the final reduction that adds them).
+hipError_t launch_pme(const Dev& d, hipStream_t st, const double* pos, int schedule, int precision);
 // pair inputs from the last forward's slot coordinates and list
 hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
                               const double* g_energy, double* d_sigma, double* d_sqrt_eps, double* d_charge, double* d_eps);

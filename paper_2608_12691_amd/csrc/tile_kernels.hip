@@ -1075,6 +1075,32 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
       t[0] = solv; t[1] = solu; t[2] = L.a[0] * a0 + L.a[1] * a2; t[3] = L.a[0] * a1;
       t[4] = a0 + a1; t[5] = a2; t[6] = L.a[2] * a0 + L.a[3] * a2; t[7] = L.a[2] * a1;
     }
+    if (d.pme_box) {
+      // PME parts of the box: partial sums in slot order, then the
+      // background part from the group charges; S-S and W-W join the
+      // lambda-independent terms, the S-W part X is scaled like the
+      // solute-solvent Coulomb pairs
+      double e[PME_NPART];
+      for (int j = 0; j < PME_NPART; ++j) e[j] = 0.0;
+      const double* pp = d.pme_part + (size_t)k * kPmeParts * PME_NPART;
+      for (int q = 0; q < kPmeParts; ++q)
+        for (int j = 0; j < PME_NPART; ++j) e[j] += pp[q * PME_NPART + j];
+      const PmeBox B = d.pme_box[k];
+      const double bg = -kKe * M_PI / (B.L[0] * B.L[1] * B.L[2] * d.pme_alpha * d.pme_alpha);
+      const double ss = (e[PME_E_SS] + e[PME_C_SS]) + 0.5 * bg * e[PME_Q_S] * e[PME_Q_S];
+      const double ww = (e[PME_E_WW] + e[PME_C_WW]) + 0.5 * bg * e[PME_Q_W] * e[PME_Q_W];
+      const double X = (e[PME_E_SW] + e[PME_C_SW]) + bg * e[PME_Q_S] * e[PME_Q_W];
+      t[0] += ww;
+      t[1] += ss;
+      if (schedule == 0) {
+        t[3] += L.a[1] * X;
+        t[7] += L.a[3] * X;
+      } else {
+        t[3] += L.a[0] * X;
+        t[4] += X;
+        t[7] += L.a[2] * X;
+      }
+    }
     t[8] = ((t[0] + t[1]) + t[2]) + t[3];
     t[9] = t[6] + t[7];
     if (terms)

@@ -192,3 +192,45 @@ def test_compute_checked_reacts_to_barrier_timeout_and_capacity():
     flags_seq[:] = [A.FLAG_BARRIER_TIMEOUT]
     assert A.Context.compute_checked(ctx, None, None)["flags"] == A.FLAG_BARRIER_TIMEOUT
     assert calls == [("compute", A.AUTO_REBUILD)]
+
+
+def test_pme_grid_planning_and_rejections(lib):
+    """PME contexts: per-box grids of 2^a 3^b 5^c points >= max(L/spacing, 2 order);
+    bad orders, spacings and splitting parameters are refused, oversized grids unsupported."""
+    from paper_2608_12691_amd import alchnb
+    pme = dict(electrostatics=alchnb.ELEC_PME, pme_order=5, pme_spacing=1.0, dsf_alpha=0.3)
+    p, keep = _params(alchnb, FF, **pme)
+    s0, k0 = _system(alchnb, 4, 20.0)
+    s1, k1 = _system(alchnb, 4, 44.85)
+    s2, k2 = _system(alchnb, 0, 23.0, types=[], sol=[])
+    st, ctx = _create(lib, p, [s0, s1, s2])
+    assert st == 0
+    dims = (ctypes.c_int32 * 3)()
+    got = []
+    for k in range(3):
+        assert lib.alch_nb_pme_grid(ctx, k, dims) == 0
+        got.append(tuple(dims))
+    assert got == [(20, 20, 20), (45, 45, 45), (24, 24, 24)]
+    assert lib.alch_nb_pme_grid(ctx, 3, dims) == 1
+    nb_pme = ctypes.c_size_t()
+    lib.alch_nb_workspace_size(ctx, ctypes.byref(nb_pme))
+    lib.alch_nb_destroy(ctx)
+    # the same boxes with DSF: no grid, a smaller workspace
+    p, keep2 = _params(alchnb, FF)
+    st, ctx = _create(lib, p, [s0, s1, s2])
+    assert st == 0 and lib.alch_nb_pme_grid(ctx, 0, dims) == 3
+    nb = ctypes.c_size_t()
+    lib.alch_nb_workspace_size(ctx, ctypes.byref(nb))
+    assert nb_pme.value > nb.value + 32 * (20 ** 3 + 45 ** 3)
+    lib.alch_nb_destroy(ctx)
+    # a coarse spacing still gives 2 order points per edge
+    p, keep3 = _params(alchnb, FF, **dict(pme, pme_spacing=50.0, pme_order=6))
+    st, ctx = _create(lib, p, [s0])
+    assert st == 0 and lib.alch_nb_pme_grid(ctx, 0, dims) == 0 and tuple(dims) == (12, 12, 12)
+    lib.alch_nb_destroy(ctx)
+    for bad, code in ((dict(pme_order=3), 1), (dict(pme_order=7), 1), (dict(pme_spacing=0.0), 1),
+                      (dict(dsf_alpha=0.0), 1), (dict(electrostatics=2), 1), (dict(pme_spacing=0.01), 3)):
+        p, keep4 = _params(alchnb, FF, **dict(pme, **bad))
+        st, ctx = _create(lib, p, [s0])
+        assert st == code, bad
+        assert not ctx.value
