@@ -102,9 +102,10 @@ struct alch_nb_ctx {
   std::vector<double2> pme_roots;
   std::vector<double> pme_bmod;
   long long pme_points = 0;
-  int pme_lines[3] = {0, 0, 0};
   int pme_tab = 0;  // entries of the axis tables
   double pme_qscale = 0;  // fixed-point units per e of the charge grids
+  int pme_tiles[3] = {0, 0, 0};
+  std::vector<PmePair> pme_pairs;
 };
 
 static alch_nb_status hip_fail(alch_nb_ctx* c, hipError_t e) {
@@ -216,8 +217,11 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
     d->pme_roots = cv.take<double2>(base, ctx->pme_tab);
     d->pme_bmod = cv.take<double>(base, ctx->pme_tab);
     d->pme_part = cv.take<double>(base, K * kPmeParts * PME_NPART);
+    d->pme_infl = cv.take<double>(base, (size_t)ctx->pme_points);
+    d->pme_const = cv.take<double>(base, 4 * K);
+    d->pme_pairs = cv.take<PmePair>(base, ctx->pme_pairs.size());
     d->pme_points = ctx->pme_points;
-    for (int a = 0; a < 3; ++a) d->pme_lines[a] = ctx->pme_lines[a];
+    for (int a = 0; a < 3; ++a) d->pme_tiles[a] = ctx->pme_tiles[a];
     d->pme_order = ctx->p.pme_order;
     d->pme_alpha = ctx->p.dsf_alpha;
     d->pme_qscale = ctx->pme_qscale;
@@ -228,6 +232,9 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
     d->pme_roots = nullptr;
     d->pme_bmod = nullptr;
     d->pme_part = nullptr;
+    d->pme_infl = nullptr;
+    d->pme_const = nullptr;
+    d->pme_pairs = nullptr;
     d->pme_points = 0;
     d->pme_order = 0;
     d->pme_alpha = 0.0;
@@ -527,7 +534,8 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
   if (p.electrostatics == ALCH_NB_ELEC_PME) {
     ctx->pme = true;
     long long pts = 0;
-    int tab = 0, lines[3] = {0, 0, 0};
+    int tab = 0, tiles[3] = {0, 0, 0};
+    int atom0 = 0;
     for (int k = 0; k < n_systems; ++k) {
       PmeBox B{};
       for (int a = 0; a < 3; ++a) {
@@ -542,8 +550,9 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
       pts += (long long)B.n[0] * B.n[1] * B.n[2];
       const int per_axis[3] = {B.n[1] * B.n[2], B.n[0] * B.n[2], B.n[0] * B.n[1]};
       for (int a = 0; a < 3; ++a) {
-        B.lines[a] = lines[a];
-        lines[a] += per_axis[a];
+        const int T = tile_lines(B.n[a]);
+        B.tiles[a] = tiles[a];
+        tiles[a] += (per_axis[a] + T - 1) / T;
         B.tab[a] = tab;
         tab += B.n[a];
         for (int i = 0; i < B.n[a]; ++i) {
@@ -554,6 +563,20 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
         ctx->pme_bmod.resize(b0 + B.n[a]);
         bspline_moduli(B.n[a], p.pme_order, ctx->pme_bmod.data() + b0);
       }
+      // excluded pairs of the box: k_e q q and their part
+      B.pair0 = (int)ctx->pme_pairs.size();
+      for (int e = 0; e < sys[k].n_excl; ++e) {
+        const int i = sys[k].excl[2 * e], j = sys[k].excl[2 * e + 1];
+        const int si = sys[k].is_solute[i], sj = sys[k].is_solute[j];
+        PmePair P{};
+        P.i = atom0 + i;
+        P.j = atom0 + j;
+        P.qq = kKe * p.charge[sys[k].type[i]] * p.charge[sys[k].type[j]];
+        P.kind = si && sj ? 0 : (!si && !sj ? 1 : 2);
+        ctx->pme_pairs.push_back(P);
+      }
+      B.npair = (int)ctx->pme_pairs.size() - B.pair0;
+      atom0 += sys[k].n_atoms;
       ctx->pme_box.push_back(B);
     }
     if (pts > (1LL << 31)) {
@@ -562,6 +585,7 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
     }
     ctx->pme_points = pts;
     ctx->pme_tab = tab;
+    for (int a = 0; a < 3; ++a) ctx->pme_tiles[a] = tiles[a];
     // charge-grid scale: a power of two that keeps the largest possible grid
     // value (the box's sum of |q_i|) below 2^62 units, at most 2^52
     double qmax = 1.0;
@@ -571,7 +595,6 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
       qmax = std::max(qmax, qs);
     }
     ctx->pme_qscale = std::exp2(std::min(52.0, std::floor(62.0 - std::log2(qmax))));
-    for (int a = 0; a < 3; ++a) ctx->pme_lines[a] = lines[a];
   }
 
   // potential constants (FP64)
@@ -713,8 +736,10 @@ alch_nb_status anb_bind(alch_nb_ctx* ctx, void* d_ws, size_t bytes, void* stream
   HIPCHK(up(d.pot64, pw, sizeof(pw)));
   if (ctx->pme) {
     HIPCHK(up(d.pme_box, ctx->pme_box.data(), sizeof(PmeBox) * ctx->pme_box.size()));
+    HIPCHK(up(d.pme_pairs, ctx->pme_pairs.data(), sizeof(PmePair) * ctx->pme_pairs.size()));
     HIPCHK(up(d.pme_roots, ctx->pme_roots.data(), sizeof(double2) * ctx->pme_roots.size()));
     HIPCHK(up(d.pme_bmod, ctx->pme_bmod.data(), sizeof(double) * ctx->pme_bmod.size()));
+    HIPCHK(launch_pme_init(d, st));
   }
   HIPCHK(launch_init(d, st));
   // the host copies must outlive the asynchronous uploads

@@ -84,28 +84,43 @@ __host__ __device__ inline uint32_t ent_pack(uint32_t imask, uint32_t kind, uint
 // spreading grids (S, W) that the first FFT pass reads and clears.  Per box
 // and axis an FFT root table exp(-2 pi i k/n) and the B-spline moduli
 // |b(m)|^2.  Partial sums per box: kPmeParts blocks of the convolution and
-// of the gather each write PME_NPART values (their own slots).  The charge
+// of the excluded-pair pass each write their own PME_NPART slots; the
+// self energies and group charges are constants of the binding.  The charge
 // grids count pme_qscale units per e, a power of two with
 // pme_qscale * max_box sum |q_i| <= 2^62 (a grid value never exceeds the
 // box's sum of |q_i|: the spline weights of an atom are at most 1), at most
 // 2^52.
 constexpr int kPmeMaxN = 512;       // grid points per edge at most
 constexpr int kPmeMinOrder = 4, kPmeMaxOrder = 6;
-constexpr int kPmeParts = 32;
+constexpr int kPmeParts = 256;  // partial-sum slots per box (one per thread of the final reduction's block)
 enum {
   PME_E_SS = 0, PME_E_WW = 1, PME_E_SW = 2,   // reciprocal parts (convolution)
-  PME_C_SS = 3, PME_C_WW = 4, PME_C_SW = 5,   // self and excluded-pair parts (gather)
-  PME_Q_S = 6, PME_Q_W = 7,                   // group charges (gather; background part)
-  PME_NPART = 8
+  PME_C_SS = 3, PME_C_WW = 4, PME_C_SW = 5,   // excluded-pair parts
+  PME_NPART = 6
 };
+// per-box constants: self energies of the two groups and their charges
+enum { PME_K_SELF_S = 0, PME_K_SELF_W = 1, PME_K_Q_S = 2, PME_K_Q_W = 3 };
 struct PmeBox {
   int n[3];          // grid points per axis
   int tab[3];        // offsets of the axis tables in pme_roots and pme_bmod
-  int lines[3];      // first line of this box in the pass along each axis (prefix over boxes)
+  int tiles[3];      // first FFT tile of this box in the pass along each axis (prefix over boxes)
+  int pair0, npair;  // its excluded pairs in pme_pairs
   int pad_;
   long long off;     // first grid point of the box
   double L[3];       // box edges
 };
+// an excluded pair of one box: global atom indices, k_e q_i q_j, and the
+// part it belongs to (0 solute-solute, 1 solvent-solvent, 2 solute-solvent)
+struct PmePair {
+  int i, j;
+  double qq;
+  int kind, pad_;
+};
+// lines of an FFT tile along an axis of n points (tile of <= 1024 points)
+__host__ __device__ inline int tile_lines(int n) {
+  const int t = 1024 / n;
+  return t < 1 ? 1 : (t > 16 ? 16 : t);
+}
 
 // Device view of the workspace.
 struct Dev {
@@ -192,8 +207,11 @@ struct Dev {
   const double2* pme_roots;  // per box and axis: exp(-2 pi i k/n), k < n
   const double* pme_bmod;    // per box and axis: |b(m)|^2
   double* pme_part;          // [K][kPmeParts][PME_NPART]
+  double* pme_infl;          // [pme_points] influence function C(m) (written once at bind)
+  double* pme_const;         // [K][4] self energies and group charges (written once at bind)
+  const PmePair* pme_pairs;  // excluded pairs of all boxes
   long long pme_points;      // grid points of all boxes
-  int pme_lines[3];          // lines of all boxes per axis
+  int pme_tiles[3];          // FFT tiles of all boxes per axis
   int pme_order;
   double pme_alpha;          // Ewald splitting parameter
   double pme_qscale;         // fixed-point units per e of the charge grids

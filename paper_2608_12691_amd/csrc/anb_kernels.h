@@ -55,6 +55,8 @@ hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int sche
 // Smooth-PME reciprocal space, self and excluded-pair parts of every box
 // (after the tile kernel, before the final reduction that adds them).
 hipError_t launch_pme(const Dev& d, hipStream_t st, const double* pos, int schedule, int precision);
+// The influence-function table and the per-box constants (at bind).
+hipError_t launch_pme_init(const Dev& d, hipStream_t st);
 // pair inputs from the last forward's slot coordinates and list
 hipError_t launch_param_grads(const Dev& d, hipStream_t st, const PotConsts& pc, int precision, int schedule,
                               const double* g_energy, double* d_sigma, double* d_sqrt_eps, double* d_charge, double* d_eps);

@@ -7,25 +7,32 @@
 // Per call, after the short-range tile kernel and before the final
 // reduction:
 //   k_pme_spread    charges -> two int64 fixed-point grids (solute S,
-//                   solvent W) with order-n cardinal B-splines, one atom per
-//                   thread; integer sums, so the grids are bit-identical
-//                   from run to run whatever the order of the atomics;
-//   k_pme_fft x3    forward complex transform of Z = Q_S + i Q_W, one line
-//                   per wave (the first pass reads and clears the integer
-//                   grids), mixed-radix 2/3/4/5 Stockham passes in LDS;
+//                   solvent W) with order-n cardinal B-splines, one block per
+//                   super-cluster: its atoms' n^3 points each are summed in an
+//                   LDS sub-grid, then added to the grid with one atomic per
+//                   point (integer sums: bit-identical from run to run);
+//   k_pme_corr      the excluded pairs' -k_e q q erf(a r)/r, one thread per
+//                   pair (the self and charge parts are constants of the
+//                   binding);
+//   forward FFT     of Z = Q_S + i Q_W along z, y, then x: a block per tile of
+//                   up to 16 adjacent lines in LDS (the first pass reads and
+//                   clears the integer grids), mixed-radix Stockham passes
+//                   (radices 5, 4, 3, 2);
 //   k_pme_convolve  splits the spectrum into those of Q_S and Q_W through
-//                   Z(-m) = conj, multiplies by the influence function C(m),
-//                   sums the S-S, W-W and S-W energies and writes
-//                   G_S + i G_W with G_S = C (S + c W), G_W = C (W + c S);
-//   k_pme_fft x3    inverse transforms: the grid then holds the potentials
-//                   dU/dQ_S (real part) and dU/dQ_W (imaginary part);
-//   k_pme_gather    per atom the force -q grad(sum_k M M M G), the self part
-//                   and the excluded pairs' -k_e q q erf(a r)/r with their
-//                   forces, into the fixed-point force sums.
+//                   Z(-m) = conj, multiplies by the influence function C(m)
+//                   (a table written at bind), sums the S-S, W-W and S-W
+//                   energies and writes G_S + i G_W with G_S = C (S + c W),
+//                   G_W = C (W + c S);
+//   inverse FFT     the grid then holds the potentials dU/dQ_S (real part)
+//                   and dU/dQ_W (imaginary part);
+//   k_pme_gather    one block per super-cluster: its sub-grid of the
+//                   potential staged in LDS, four threads per atom summing
+//                   -q grad(sum_k M M M G) into the fixed-point force sums.
 // Energies leave as per-box partial sums in fixed slots; the final
 // reduction adds them in order (deterministic).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "anb_kernels.h"
@@ -34,7 +41,8 @@ namespace anb {
 namespace {
 
 constexpr int kPmeBlk = 256;
-constexpr int kFftWave = 64;
+constexpr int kTilePts = 1024;  // points of an FFT tile (T(n) lines of n points)
+static_assert(kPmeMaxN <= kTilePts, "a tile holds at least one line");
 
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -121,67 +129,232 @@ __device__ inline void block_sums(double (&v)[V], double (*red)[V]) {
 
 // ---------------------------------------------------------------- spreading
 
-template <int N>
-__global__ void __launch_bounds__(kPmeBlk) k_pme_spread(Dev d, const double* __restrict__ xin) {
-  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < d.n_atoms; a += gridDim.x * blockDim.x) {
-    const int k = d.atom_rep[a];
-    const PmeBox B = d.pme_box[k];
-    const double q = d.type_q[d.atom_type[a]];
-    const bool sol = d.grids[d.atom_grid[a]].is_solute != 0;
-    int i0[3];
-    double th[3][N], dth[3][N];
+// Block (part, box): the excluded pairs of the box in kPmeParts equal runs,
+// one thread per pair: -k_e q_i q_j erf(a r)/r by minimum image and its
+// forces (the S-W pairs' scaled by c).  Partial sums into the part's slots.
+__global__ void __launch_bounds__(kPmeBlk) k_pme_corr(Dev d, const double* __restrict__ xin, int schedule,
+                                                      double fscale) {
+  __shared__ double red[kPmeBlk / 64][3];
+  const int k = blockIdx.y, part = blockIdx.x;
+  const PmeBox B = d.pme_box[k];
+  const int p0 = B.pair0 + (int)((long long)B.npair * part / kPmeParts);
+  const int p1 = B.pair0 + (int)((long long)B.npair * (part + 1) / kPmeParts);
+  const double c = lam_c(d.lam[k], schedule);
+  const double alpha = d.pme_alpha;
+  const double c2a = 2.0 * alpha / sqrt(M_PI);
+  const int slots = d.sc_cap * kSc;
+  double e[3] = {0.0, 0.0, 0.0};  // S-S, W-W, S-W
+  for (int q = p0 + (int)threadIdx.x; q < p1; q += blockDim.x) {
+    const PmePair P = d.pme_pairs[q];
+    double dv[3], r2 = 0.0;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double w;
-      i0[c] = grid_coord(xin[3 * a + c], B.L[c], B.n[c], w);
-      spline_weights<N>(w, th[c], dth[c]);
+    for (int cc = 0; cc < 3; ++cc) {
+      double u = xin[3 * P.j + cc] - xin[3 * P.i + cc];
+      u -= B.L[cc] * rint(u / B.L[cc]);
+      dv[cc] = u;
+      r2 += u * u;
     }
-    unsigned long long* g = d.pme_q + (sol ? 0 : d.pme_points) + B.off;
-    const int n1 = B.n[1], n2 = B.n[2];
+    const double r = sqrt(r2);
+    const double er = erf(alpha * r);
+    const double v = -P.qq * er / r;
+    // dv/dr = -k_e q q [2a/sqrt(pi) exp(-a^2 r^2)/r - erf(a r)/r^2]
+    const double dvdr = -P.qq * (c2a * exp(-alpha * alpha * r2) / r - er / r2);
+    e[P.kind] += v;
+    const double sf = (P.kind == 2 ? c : 1.0) * dvdr / r;
+    // F_i = -dv/dx_i = sf d, F_j = -sf d (d = x_j - x_i)
+    const int si = d.atom_slot[P.i], sj = d.atom_slot[P.j];
 #pragma unroll
-    for (int x = 0; x < N; ++x) {
-      int ix = i0[0] - x;
-      ix += ix < 0 ? B.n[0] : 0;
+    for (int cc = 0; cc < 3; ++cc) {
+      add_fixed(d.ffix + (size_t)cc * slots + si, sf * dv[cc], fscale, d.flags);
+      add_fixed(d.ffix + (size_t)cc * slots + sj, -sf * dv[cc], fscale, d.flags);
+    }
+  }
+  block_sums<3>(e, red);
+  if (threadIdx.x == 0) {
+    double* o = d.pme_part + ((size_t)k * kPmeParts + part) * PME_NPART;
+    o[PME_C_SS] = e[0];
+    o[PME_C_WW] = e[1];
+    o[PME_C_SW] = e[2];
+  }
+}
+
+// ------------------------------------------------- super-cluster sub-grids
+
+// A super-cluster's 64 slots are a compact piece of one box and one group
+// (the list build's spatial order): the grid points their splines touch
+// form a small block of the grid.  The spreading and the gather of a
+// super-cluster work on that block in LDS, so that each of its points costs
+// one global access instead of one per atom reaching it.
+constexpr int kSubMax = 4096;  // points of a super-cluster's LDS sub-grid at most
+
+// Per-block description of a super-cluster's sub-grid (in LDS).
+struct ScSub {
+  int k, sol, n;        // box, group (1 = solute), valid slots
+  int ref[3];           // grid index of the first valid slot's atom
+  int lo[3], ext[3];    // lowest unwrapped offset (spline support included) and extent
+  int size;             // ext[0] ext[1] ext[2]
+};
+
+__device__ inline int wrap_half(int v, int n) {  // v in (-n, n) -> (-n/2, n/2]
+  if (v > n / 2) v -= n;
+  else if (v <= -(n + 1) / 2) v += n;
+  return v;
+}
+
+// Wave 0 reads super-cluster s: per slot its atom, charge, grid offset from
+// the reference (unwrapped across the box edge) and spline weights and
+// derivatives; then the sub-grid.  All threads return the header (n = 0: empty super-cluster).
+template <int N>
+__device__ inline void sc_setup(const Dev& d, const double* __restrict__ xin, int s, int* s_atom,
+                                int (*s_off)[3], double (*s_th)[3][N], double (*s_dth)[3][N], double* s_q, ScSub& S) {
+  if (threadIdx.x < kSc) {
+    const int l = threadIdx.x;
+    const int a = d.slot_atom[s * kSc + l];
+    const unsigned long long valid = __ballot(a >= 0);
+    if (valid == 0) {
+      if (l == 0) S.n = 0;
+    } else {
+      const int first = __builtin_ctzll(valid);
+      const int a0 = __builtin_amdgcn_readlane(a, first);
+      const int k = d.atom_rep[a0];
+      const PmeBox B = d.pme_box[k];
+      int off[3] = {0, 0, 0};
+      double w[3] = {0.0, 0.0, 0.0};
+      int mn[3], mx[3];
 #pragma unroll
-      for (int y = 0; y < N; ++y) {
-        int iy = i0[1] - y;
-        iy += iy < 0 ? n1 : 0;
-        const double wxy = q * d.pme_qscale * th[0][x] * th[1][y];
-        unsigned long long* row = g + ((long long)ix * n1 + iy) * n2;
+      for (int c = 0; c < 3; ++c) {
+        int i = 0;
+        if (a >= 0) i = grid_coord(xin[3 * a + c], B.L[c], B.n[c], w[c]);
+        const int ref = __builtin_amdgcn_readlane(i, first);
+        off[c] = a >= 0 ? wrap_half(i - ref, B.n[c]) : 0;
+        int lo = a >= 0 ? off[c] - (N - 1) : 1 << 30, hi = a >= 0 ? off[c] : -(1 << 30);
 #pragma unroll
-        for (int z = 0; z < N; ++z) {
-          int iz = i0[2] - z;
-          iz += iz < 0 ? n2 : 0;
-          atomicAdd(row + iz, (unsigned long long)__double2ll_rn(wxy * th[2][z]));
+        for (int o = 32; o >= 1; o >>= 1) {
+          lo = min(lo, __shfl_xor(lo, o));
+          hi = max(hi, __shfl_xor(hi, o));
+        }
+        mn[c] = lo;
+        mx[c] = hi;
+        if (l == 0) S.ref[c] = ref;
+      }
+      s_atom[l] = a;
+      s_q[l] = a >= 0 ? d.type_q[d.atom_type[a]] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        s_off[l][c] = off[c];
+        double th[N], dth[N];
+        spline_weights<N>(w[c], th, dth);
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          s_th[l][c][j] = th[j];
+          s_dth[l][c][j] = dth[j];
         }
       }
+      if (l == 0) {
+        S.k = k;
+        S.sol = d.grids[d.atom_grid[a0]].is_solute != 0;
+        S.n = __popcll(valid);
+        long long size = 1;
+        for (int c = 0; c < 3; ++c) {
+          S.lo[c] = mn[c];
+          S.ext[c] = mx[c] - mn[c] + 1;
+          size *= S.ext[c];
+        }
+        S.size = size <= kSubMax ? (int)size : -1;  // -1: too large for LDS
+      }
     }
+  }
+  __syncthreads();
+}
+
+// Global grid index of sub-grid point (u0, u1, u2).
+__device__ inline long long sub_to_grid(const ScSub& S, const PmeBox& B, int u0, int u1, int u2) {
+  int g[3];
+  const int u[3] = {u0, u1, u2};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    int v = (S.ref[c] + S.lo[c] + u[c]) % B.n[c];
+    g[c] = v < 0 ? v + B.n[c] : v;
+  }
+  return ((long long)g[0] * B.n[1] + g[1]) * B.n[2] + g[2];
+}
+
+// The spreading of super-cluster blockIdx.x: LDS sub-grid, then one global
+// atomic per non-zero point (straight global atomics when the sub-grid is
+// too large).
+template <int N>
+__global__ void __launch_bounds__(kPmeBlk) k_pme_spread(Dev d, const double* __restrict__ xin) {
+  __shared__ int s_atom[kSc];
+  __shared__ int s_off[kSc][3];
+  __shared__ double s_th[kSc][3][N], s_dth[kSc][3][N];
+  __shared__ double s_q[kSc];
+  __shared__ ScSub S;
+  __shared__ unsigned long long sub[kSubMax];
+  const int s = blockIdx.x;
+  sc_setup<N>(d, xin, s, s_atom, s_off, s_th, s_dth, s_q, S);
+  if (S.n == 0) return;
+  const PmeBox B = d.pme_box[S.k];
+  const bool lds = S.size > 0;
+  const int e1 = S.ext[1], e2 = S.ext[2];
+  if (lds) {
+    for (int e = threadIdx.x; e < S.size; e += blockDim.x) sub[e] = 0ull;
+    __syncthreads();
+  }
+  unsigned long long* grid = d.pme_q + (S.sol ? 0 : d.pme_points) + B.off;
+  const double qs = d.pme_qscale;
+  for (int idx = threadIdx.x; idx < kSc * N * N; idx += blockDim.x) {
+    const int sl = idx / (N * N);
+    if (s_atom[sl] < 0) continue;
+    const int xy = idx - sl * (N * N);
+    const int x = xy / N, y = xy - (xy / N) * N;
+    const double wxy = s_q[sl] * qs * s_th[sl][0][x] * s_th[sl][1][y];
+    const int u0 = s_off[sl][0] - x - S.lo[0], u1 = s_off[sl][1] - y - S.lo[1];
+#pragma unroll
+    for (int z = 0; z < N; ++z) {
+      const int u2 = s_off[sl][2] - z - S.lo[2];
+      const unsigned long long v = (unsigned long long)__double2ll_rn(wxy * s_th[sl][2][z]);
+      if (lds) atomicAdd(&sub[((long long)u0 * e1 + u1) * e2 + u2], v);
+      else atomicAdd(grid + sub_to_grid(S, B, u0, u1, u2), v);
+    }
+  }
+  if (!lds) return;
+  __syncthreads();
+  for (int e = threadIdx.x; e < S.size; e += blockDim.x) {
+    const unsigned long long v = sub[e];
+    if (v == 0ull) continue;
+    const int u0 = e / (e1 * e2), r = e - u0 * (e1 * e2);
+    const int u1 = r / e2, u2 = r - u1 * e2;
+    atomicAdd(grid + sub_to_grid(S, B, u0, u1, u2), v);
   }
 }
 
 // --------------------------------------------------------------------- FFT
 
-// One Stockham pass of radix R over a line of n points in LDS: butterfly j
-// (< n/R) reads src[j + r n/R], multiplies by the twiddles
-// exp(-+2 pi i r k/(Ns R)) with k = j mod Ns, takes the R-point DFT and
-// writes dst[(j/Ns) Ns R + k + q Ns].
+// One Stockham pass of radix R over `lines` lines of n points in LDS
+// (point i of line l at l * lstride + i * estride), the butterflies of all
+// lines spread over the block.
 template <int R>
-__device__ inline void fft_pass(const double2* __restrict__ src, double2* __restrict__ dst, int n, int Ns,
-                                const double2* __restrict__ W, bool inv) {
+__device__ inline void fft_stage(const double2* __restrict__ src, double2* __restrict__ dst, int n, int Ns,
+                                 int lines, int lstride, int estride, const double2* __restrict__ W, bool inv) {
   const int m = n / R;
   const int step = n / (Ns * R);
-  for (int j = threadIdx.x; j < m; j += kFftWave) {
+  const int total = lines * m;
+  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int line = idx / m, j = idx - line * m;
     const int k = j % Ns;
+    const double2* s = src + line * lstride;
     double2 v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[j + r * m];
+    for (int r = 0; r < R; ++r) v[r] = s[(j + r * m) * estride];
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      double2 t = W[(r * k * step) % n];
+      double2 t = W[r * k * step];
       if (inv) t.y = -t.y;
       v[r] = cmul(v[r], t);
     }
-    double2 o[R];
+    // the R-point DFT, each output straight to LDS (no second register array)
+    double2* o_line = dst + line * lstride;
+    const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       double2 acc = v[0];
@@ -193,86 +366,157 @@ __device__ inline void fft_pass(const double2* __restrict__ src, double2* __rest
         acc.x += p.x;
         acc.y += p.y;
       }
-      o[q] = acc;
+      o_line[(base + q * Ns) * estride] = acc;
     }
-    const int base = (j / Ns) * Ns * R + k;
-#pragma unroll
-    for (int q = 0; q < R; ++q) dst[base + q * Ns] = o[q];
   }
 }
 
-// One line per block of one wave: lines of the pass along `axis` are
-// numbered box by box (PmeBox::lines); forward (inv = 0) or inverse
-// (unnormalised) transform in place.  first: read the line from the two
-// integer grids (Q_S + i Q_W) and clear them.
-__global__ void __launch_bounds__(kFftWave) k_pme_fft(Dev d, int axis, int inv, int first) {
-  __shared__ double2 buf[2][kPmeMaxN];
-  const int line = blockIdx.x;
-  // the box holding this line (boxes in order, prefix of lines per box)
-  int lo = 0, hi = d.n_reps - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (d.pme_box[mid].lines[axis] <= line) lo = mid;
-    else hi = mid - 1;
-  }
-  const PmeBox B = d.pme_box[lo];
-  const int l = line - B.lines[axis];
-  const int n = B.n[axis], n1 = B.n[1], n2 = B.n[2];
-  long long base, stride;
-  if (axis == 2) {  // l = ix n1 + iy
-    base = (long long)l * n2;
-    stride = 1;
-  } else if (axis == 1) {  // l = ix n2 + iz
-    base = (long long)(l / n2) * n1 * n2 + (l % n2);
-    stride = n2;
-  } else {  // l = iy n2 + iz
-    base = l;
-    stride = (long long)n1 * n2;
-  }
-  double2* g = d.pme_grid + B.off + base;
-  if (first) {
-    const double inv_q = 1.0 / d.pme_qscale;
-    unsigned long long* qs = d.pme_q + B.off + base;
-    unsigned long long* qw = qs + d.pme_points;
-    for (int j = threadIdx.x; j < n; j += kFftWave) {
-      const long long s = (long long)qs[j * stride], w = (long long)qw[j * stride];
-      qs[j * stride] = 0ull;
-      qw[j * stride] = 0ull;
-      buf[0][j] = make_double2((double)s * inv_q, (double)w * inv_q);
-    }
-  } else {
-    for (int j = threadIdx.x; j < n; j += kFftWave) buf[0][j] = g[j * stride];
-  }
-  __syncthreads();
-  const double2* W = d.pme_roots + B.tab[axis];
-  int src = 0, Ns = 1, rem = n;
+// Transforms of `lines` lines of n points held in b0 (src = 0) or b1
+// (src = 1); the result ends in the one src names after the call (it flips
+// with every pass).
+__device__ inline void fft_lines(double2* b0, double2* b1, int& src, int n, int lines, int lstride, int estride,
+                                 const double2* W, bool inv) {
+  int Ns = 1, rem = n;
   while (rem > 1) {
-    if (rem % 4 == 0) {
-      fft_pass<4>(buf[src], buf[src ^ 1], n, Ns, W, inv != 0);
-      Ns *= 4;
-      rem /= 4;
+    double2* from = src ? b1 : b0;
+    double2* to = src ? b0 : b1;
+    int R;
+    if (rem % 5 == 0) {
+      R = 5;
+      fft_stage<5>(from, to, n, Ns, lines, lstride, estride, W, inv);
+    } else if (rem % 4 == 0) {
+      R = 4;
+      fft_stage<4>(from, to, n, Ns, lines, lstride, estride, W, inv);
     } else if (rem % 2 == 0) {
-      fft_pass<2>(buf[src], buf[src ^ 1], n, Ns, W, inv != 0);
-      Ns *= 2;
-      rem /= 2;
+      R = 2;
+      fft_stage<2>(from, to, n, Ns, lines, lstride, estride, W, inv);
     } else if (rem % 3 == 0) {
-      fft_pass<3>(buf[src], buf[src ^ 1], n, Ns, W, inv != 0);
-      Ns *= 3;
-      rem /= 3;
+      R = 3;
+      fft_stage<3>(from, to, n, Ns, lines, lstride, estride, W, inv);
     } else {
-      fft_pass<5>(buf[src], buf[src ^ 1], n, Ns, W, inv != 0);
-      Ns *= 5;
-      rem /= 5;
+      R = 5;
+      fft_stage<5>(from, to, n, Ns, lines, lstride, estride, W, inv);
     }
+    Ns *= R;
+    rem /= R;
     src ^= 1;
     __syncthreads();
   }
-  for (int j = threadIdx.x; j < n; j += kFftWave) g[j * stride] = buf[src][j];
+}
+
+// Lines of the pass along `axis` per box: z rows (ix, iy), y columns
+// (ix, iz) and x columns (iy, iz), numbered so that consecutive lines are
+// adjacent in memory; a block transforms a tile of T(n) consecutive lines.
+__device__ inline long long line_addr(int axis, const PmeBox& B, int l, int j) {
+  const int n1 = B.n[1], n2 = B.n[2];
+  if (axis == 2) return (long long)l * n2 + j;
+  const int a = l / n2, iz = l - a * n2;
+  if (axis == 1) return ((long long)a * n1 + j) * n2 + iz;
+  return ((long long)j * n1 + a) * n2 + iz;
+}
+
+// Block t of the pass along `axis` (tiles numbered box by box,
+// PmeBox::tiles): its lines staged in LDS (the root table too), the
+// Stockham passes, the lines written back; forward (inv = 0) or inverse
+// (unnormalised).  first: the lines come from the two integer grids
+// (Q_S + i Q_W), which are cleared.  Loads and stores run along the
+// memory-contiguous direction (points of a z row; lines of a y or x tile).
+__global__ void __launch_bounds__(kPmeBlk) k_pme_fft(Dev d, int axis, int inv, int first) {
+  __shared__ double2 b0[kTilePts], b1[kTilePts], W[kPmeMaxN];
+  int lo = 0, hi = d.n_reps - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d.pme_box[mid].tiles[axis] <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const PmeBox B = d.pme_box[lo];
+  // (selects, not a private array indexed at run time, which would live in scratch memory)
+  const int n = axis == 0 ? B.n[0] : (axis == 1 ? B.n[1] : B.n[2]);
+  const int tab = axis == 0 ? B.tab[0] : (axis == 1 ? B.tab[1] : B.tab[2]);
+  const int tile0 = axis == 0 ? B.tiles[0] : (axis == 1 ? B.tiles[1] : B.tiles[2]);
+  const int lines = axis == 2 ? B.n[0] * B.n[1] : (axis == 1 ? B.n[0] * B.n[2] : B.n[1] * B.n[2]);
+  const int T = tile_lines(n);
+  const int l0 = ((int)blockIdx.x - tile0) * T;
+  const int nl = min(T, lines - l0);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) W[e] = d.pme_roots[tab + e];
+  const int np = nl * n;
+  double2* g = d.pme_grid + B.off;
+  for (int e = threadIdx.x; e < np; e += blockDim.x) {
+    const int li = axis == 2 ? e / n : e % nl, j = axis == 2 ? e - li * n : e / nl;
+    const long long a = line_addr(axis, B, l0 + li, j);
+    double2 v;
+    if (first) {
+      unsigned long long* qs = d.pme_q + B.off + a;
+      unsigned long long* qw = qs + d.pme_points;
+      const long long x = (long long)*qs, y = (long long)*qw;
+      *qs = 0ull;
+      *qw = 0ull;
+      const double inv_q = 1.0 / d.pme_qscale;
+      v = make_double2((double)x * inv_q, (double)y * inv_q);
+    } else {
+      v = g[a];
+    }
+    b0[li * n + j] = v;
+  }
+  __syncthreads();
+  int src = 0;
+  fft_lines(b0, b1, src, n, nl, n, 1, W, inv != 0);
+  const double2* res = src ? b1 : b0;
+  for (int e = threadIdx.x; e < np; e += blockDim.x) {
+    const int li = axis == 2 ? e / n : e % nl, j = axis == 2 ? e - li * n : e / nl;
+    g[line_addr(axis, B, l0 + li, j)] = res[li * n + j];
+  }
+}
+
+// At bind: the influence function C(m) = k_e/(pi V) exp(-pi^2 |m|^2/a^2)/|m|^2
+// B(m) of every grid point (C(0) = 0), and per box (block k < K, fixed
+// order) the self energies -k_e a/sqrt(pi) sum q^2 of both groups and their
+// charges (the background part's input).
+__global__ void __launch_bounds__(kPmeBlk) k_pme_init(Dev d) {
+  __shared__ double red[kPmeBlk / 64][4];
+  for (int k = 0; k < d.n_reps; ++k) {
+    const PmeBox B = d.pme_box[k];
+    const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
+    const long long P = (long long)n0 * n1 * n2;
+    const double pref = kKe / (M_PI * B.L[0] * B.L[1] * B.L[2]);
+    const double e2 = M_PI * M_PI / (d.pme_alpha * d.pme_alpha);
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+         p += (long long)gridDim.x * blockDim.x) {
+      const int i0 = (int)(p / ((long long)n1 * n2));
+      const int r = (int)(p - (long long)i0 * n1 * n2);
+      const int i1 = r / n2, i2 = r - i1 * n2;
+      const int s0 = i0 <= n0 / 2 ? i0 : i0 - n0, s1 = i1 <= n1 / 2 ? i1 : i1 - n1, s2 = i2 <= n2 / 2 ? i2 : i2 - n2;
+      const double mx = s0 / B.L[0], my = s1 / B.L[1], mz = s2 / B.L[2];
+      const double m2 = mx * mx + my * my + mz * mz;
+      d.pme_infl[B.off + p] = p == 0 ? 0.0
+                                     : pref * exp(-e2 * m2) / m2 *
+                                           (d.pme_bmod[B.tab[0] + i0] * d.pme_bmod[B.tab[1] + i1] *
+                                            d.pme_bmod[B.tab[2] + i2]);
+    }
+  }
+  for (int k = blockIdx.x; k < d.n_reps; k += gridDim.x) {
+    const ReplicaInfo R = d.reps[k];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};  // sum q^2 S, W; sum q S, W
+    for (int a = R.atom_off + (int)threadIdx.x; a < R.atom_off + R.n_atoms; a += blockDim.x) {
+      const double q = d.type_q[d.atom_type[a]];
+      const bool sol = d.grids[d.atom_grid[a]].is_solute != 0;
+      v[sol ? 0 : 1] += q * q;
+      v[sol ? 2 : 3] += q;
+    }
+    block_sums<4>(v, red);
+    if (threadIdx.x == 0) {
+      const double self = -kKe * d.pme_alpha / sqrt(M_PI);
+      double* o = d.pme_const + 4 * (size_t)k;
+      o[PME_K_SELF_S] = self * v[0];
+      o[PME_K_SELF_W] = self * v[1];
+      o[PME_K_Q_S] = v[2];
+      o[PME_K_Q_W] = v[3];
+    }
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------- convolution
-
-__device__ inline int signed_index(int i, int n) { return i <= n / 2 ? i : i - n; }
 
 // Block (part, box): points [P part/kPmeParts, P (part+1)/kPmeParts) of the
 // box; each point m with its partner -m handled by the smaller index.
@@ -284,13 +528,8 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_convolve(Dev d, int schedule) {
   const long long P = (long long)n0 * n1 * n2;
   const long long p0 = P * part / kPmeParts, p1 = P * (part + 1) / kPmeParts;
   const double c = lam_c(d.lam[k], schedule);
-  const double V = B.L[0] * B.L[1] * B.L[2];
-  const double pref = kKe / (M_PI * V);
-  const double e2 = M_PI * M_PI / (d.pme_alpha * d.pme_alpha);
-  const double* b0 = d.pme_bmod + B.tab[0];
-  const double* b1 = d.pme_bmod + B.tab[1];
-  const double* b2 = d.pme_bmod + B.tab[2];
   double2* g = d.pme_grid + B.off;
+  const double* infl = d.pme_infl + B.off;
   double e[3] = {0.0, 0.0, 0.0};
   for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
     const int i0 = (int)(p / ((long long)n1 * n2));
@@ -300,16 +539,10 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_convolve(Dev d, int schedule) {
     const long long pp = ((long long)j0 * n1 + j1) * n2 + j2;
     if (pp < p) continue;  // the partner's thread takes the pair
     const double2 Z = g[p], Zc = g[pp];
+    const double C = infl[p];
     // spectra of Q_S and Q_W at m (both grids are real)
     const double2 S = make_double2(0.5 * (Z.x + Zc.x), 0.5 * (Z.y - Zc.y));
     const double2 Wv = make_double2(0.5 * (Z.y + Zc.y), -0.5 * (Z.x - Zc.x));
-    double C = 0.0;
-    if (p != 0) {
-      const double mx = signed_index(i0, n0) / B.L[0], my = signed_index(i1, n1) / B.L[1],
-                   mz = signed_index(i2, n2) / B.L[2];
-      const double m2 = mx * mx + my * my + mz * mz;
-      C = pref * exp(-e2 * m2) / m2 * (b0[i0] * b1[i1] * b2[i2]);
-    }
     const double mult = pp == p ? 1.0 : 2.0;
     e[0] += mult * 0.5 * C * (S.x * S.x + S.y * S.y);
     e[1] += mult * 0.5 * C * (Wv.x * Wv.x + Wv.y * Wv.y);
@@ -330,124 +563,95 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_convolve(Dev d, int schedule) {
 
 // ------------------------------------------------------------------ gather
 
-// Block (part, box): atoms of the box in kPmeParts equal runs.  The
-// reciprocal force of each atom, its self energy and charge, and its
-// excluded pairs with later atoms (each pair once), the S-W pairs' forces
-// scaled by c.
+// One block per super-cluster: its sub-grid of the group's potential (G_S
+// for a solute super-cluster, G_W otherwise) staged in LDS, then four
+// threads per slot: thread p takes the rows (x, y) = p, p + 4, ... (< n^2)
+// and sums each z row against the spline weights and their derivatives; the
+// three force components are summed over the four threads and added to the
+// slot's fixed-point force sums.
 template <int N>
-__global__ void __launch_bounds__(kPmeBlk) k_pme_gather(Dev d, const double* __restrict__ xin, int schedule,
-                                                        double fscale) {
-  __shared__ double red[kPmeBlk / 64][5];
-  const int k = blockIdx.y, part = blockIdx.x;
-  const ReplicaInfo R = d.reps[k];
-  const PmeBox B = d.pme_box[k];
-  const int a0 = R.atom_off + (int)((long long)R.n_atoms * part / kPmeParts);
-  const int a1 = R.atom_off + (int)((long long)R.n_atoms * (part + 1) / kPmeParts);
-  const double c = lam_c(d.lam[k], schedule);
-  const double alpha = d.pme_alpha;
-  const double self = -kKe * alpha / sqrt(M_PI);
-  const double c2a = 2.0 * alpha / sqrt(M_PI);
-  const int slots = d.sc_cap * kSc;
-  const int n1 = B.n[1], n2 = B.n[2];
-  const double sc[3] = {B.n[0] / B.L[0], B.n[1] / B.L[1], B.n[2] / B.L[2]};
-  double e[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // self+excl S-S, W-W, excl S-W, charge S, W
-  for (int a = a0 + (int)threadIdx.x; a < a1; a += blockDim.x) {
-    const double q = d.type_q[d.atom_type[a]];
-    const bool sol = d.grids[d.atom_grid[a]].is_solute != 0;
-    const double xa[3] = {xin[3 * a], xin[3 * a + 1], xin[3 * a + 2]};
-    int i0[3];
-    double th[3][N], dth[3][N];
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      double w;
-      i0[cc] = grid_coord(xa[cc], B.L[cc], B.n[cc], w);
-      spline_weights<N>(w, th[cc], dth[cc]);
+__global__ void __launch_bounds__(kPmeBlk) k_pme_gather(Dev d, const double* __restrict__ xin, double fscale) {
+  __shared__ int s_atom[kSc];
+  __shared__ int s_off[kSc][3];
+  __shared__ double s_th[kSc][3][N], s_dth[kSc][3][N];
+  __shared__ double s_q[kSc];
+  __shared__ ScSub S;
+  __shared__ double sub[kSubMax];
+  const int s = blockIdx.x;
+  sc_setup<N>(d, xin, s, s_atom, s_off, s_th, s_dth, s_q, S);
+  if (S.n == 0) return;
+  const PmeBox B = d.pme_box[S.k];
+  const bool lds = S.size > 0;
+  const int e1 = S.ext[1], e2 = S.ext[2];
+  const double2* grid = d.pme_grid + B.off;
+  if (lds) {
+    for (int e = threadIdx.x; e < S.size; e += blockDim.x) {
+      const int u0 = e / (e1 * e2), r = e - u0 * (e1 * e2);
+      const int u1 = r / e2, u2 = r - u1 * e2;
+      const double2 v = grid[sub_to_grid(S, B, u0, u1, u2)];
+      sub[e] = S.sol ? v.x : v.y;
     }
-    const double2* g = d.pme_grid + B.off;
-    double f[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int x = 0; x < N; ++x) {
-      int ix = i0[0] - x;
-      ix += ix < 0 ? B.n[0] : 0;
-#pragma unroll
-      for (int y = 0; y < N; ++y) {
-        int iy = i0[1] - y;
-        iy += iy < 0 ? n1 : 0;
-        const double2* row = g + ((long long)ix * n1 + iy) * n2;
+    __syncthreads();
+  }
+  const int slots = d.sc_cap * kSc;
+  for (int base = 0; base < kSc * 4; base += blockDim.x) {
+    const int t = base + (int)threadIdx.x;
+    const int sl = t >> 2, p = t & 3;
+    const bool have = sl < kSc && s_atom[sl] >= 0;
+    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+    if (have) {
+      for (int xy = p; xy < N * N; xy += 4) {
+        const int x = xy / N, y = xy - (xy / N) * N;
+        const int u0 = s_off[sl][0] - x - S.lo[0], u1 = s_off[sl][1] - y - S.lo[1];
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int z = 0; z < N; ++z) {
-          int iz = i0[2] - z;
-          iz += iz < 0 ? n2 : 0;
-          const double2 v = row[iz];
-          const double G = sol ? v.x : v.y;
-          s0 += th[2][z] * G;
-          s1 += dth[2][z] * G;
+          const int u2 = s_off[sl][2] - z - S.lo[2];
+          double G;
+          if (lds) {
+            G = sub[((long long)u0 * e1 + u1) * e2 + u2];
+          } else {
+            const double2 v = grid[sub_to_grid(S, B, u0, u1, u2)];
+            G = S.sol ? v.x : v.y;
+          }
+          s0 += s_th[sl][2][z] * G;
+          s1 += s_dth[sl][2][z] * G;
         }
-        f[0] += dth[0][x] * th[1][y] * s0;
-        f[1] += th[0][x] * dth[1][y] * s0;
-        f[2] += th[0][x] * th[1][y] * s1;
+        const double tx = s_th[sl][0][x], dtx = s_dth[sl][0][x], ty = s_th[sl][1][y], dty = s_dth[sl][1][y];
+        f0 += dtx * ty * s0;
+        f1 += tx * dty * s0;
+        f2 += tx * ty * s1;
       }
     }
-    double fa[3] = {-q * sc[0] * f[0], -q * sc[1] * f[1], -q * sc[2] * f[2]};
-    e[sol ? 0 : 1] += self * q * q;
-    e[sol ? 3 : 4] += q;
-    // excluded pairs (a, j > a): -k_e q_a q_j erf(a r)/r by minimum image
-    for (int x = d.excl_start[a]; x < d.excl_start[a + 1]; ++x) {
-      const int j = d.excl_j[x];
-      const double qj = d.type_q[d.atom_type[j]];
-      const bool solj = d.grids[d.atom_grid[j]].is_solute != 0;
-      double dv[3], r2 = 0.0;
+    // sum over the slot's four threads (lanes 4m .. 4m+3 of one wave)
 #pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        double t = xin[3 * j + cc] - xa[cc];
-        t -= B.L[cc] * rint(t / B.L[cc]);
-        dv[cc] = t;
-        r2 += t * t;
-      }
-      const double r = sqrt(r2);
-      const double er = erf(alpha * r);
-      const double qq = kKe * q * qj;
-      const double v = -qq * er / r;
-      // dv/dr = -k_e q q [2a/sqrt(pi) exp(-a^2 r^2)/r - erf(a r)/r^2]
-      const double dvdr = -qq * (c2a * exp(-alpha * alpha * r2) / r - er / r2);
-      const bool cross = sol != solj;
-      e[cross ? 2 : (sol ? 0 : 1)] += v;
-      const double s = (cross ? c : 1.0) * dvdr / r;
-      // F_a = -dv/dx_a = s d, F_j = -s d (d = x_j - x_a)
-      const int slj = d.atom_slot[j];
-#pragma unroll
-      for (int cc = 0; cc < 3; ++cc) {
-        fa[cc] += s * dv[cc];
-        add_fixed(d.ffix + (size_t)cc * slots + slj, -s * dv[cc], fscale, d.flags);
-      }
+    for (int o = 1; o <= 2; o <<= 1) {
+      f0 += __shfl_xor(f0, o);
+      f1 += __shfl_xor(f1, o);
+      f2 += __shfl_xor(f2, o);
     }
-    const int sl = d.atom_slot[a];
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) add_fixed(d.ffix + (size_t)cc * slots + sl, fa[cc], fscale, d.flags);
-  }
-  block_sums<5>(e, red);
-  if (threadIdx.x == 0) {
-    double* o = d.pme_part + ((size_t)k * kPmeParts + part) * PME_NPART;
-    o[PME_C_SS] = e[0];
-    o[PME_C_WW] = e[1];
-    o[PME_C_SW] = e[2];
-    o[PME_Q_S] = e[3];
-    o[PME_Q_W] = e[4];
+    if (have && p == 0) {
+      const double q = s_q[sl];
+      const int gs = s * kSc + sl;
+      add_fixed(d.ffix + gs, -q * (B.n[0] / B.L[0]) * f0, fscale, d.flags);
+      add_fixed(d.ffix + (size_t)slots + gs, -q * (B.n[1] / B.L[1]) * f1, fscale, d.flags);
+      add_fixed(d.ffix + 2 * (size_t)slots + gs, -q * (B.n[2] / B.L[2]) * f2, fscale, d.flags);
+    }
   }
 }
 
 template <int N>
 hipError_t launch_pme_order(const Dev& d, hipStream_t st, const double* pos, int schedule, double fscale) {
-  const int gs = max(1, min(2048, (d.n_atoms + kPmeBlk - 1) / kPmeBlk));
-  hipLaunchKernelGGL(k_pme_spread<N>, dim3(gs), dim3(kPmeBlk), 0, st, d, pos);
+  const dim3 parts(kPmeParts, d.n_reps);
+  hipLaunchKernelGGL(k_pme_spread<N>, dim3(d.sc_cap), dim3(kPmeBlk), 0, st, d, pos);
+  hipLaunchKernelGGL(k_pme_corr, parts, dim3(kPmeBlk), 0, st, d, pos, schedule, fscale);
   const int fwd[3] = {2, 1, 0};
   for (int i = 0; i < 3; ++i)
-    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_lines[fwd[i]]), dim3(kFftWave), 0, st, d, fwd[i], 0, i == 0 ? 1 : 0);
-  hipLaunchKernelGGL(k_pme_convolve, dim3(kPmeParts, d.n_reps), dim3(kPmeBlk), 0, st, d, schedule);
+    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[fwd[i]]), dim3(kPmeBlk), 0, st, d, fwd[i], 0, i == 0 ? 1 : 0);
+  hipLaunchKernelGGL(k_pme_convolve, parts, dim3(kPmeBlk), 0, st, d, schedule);
   for (int i = 2; i >= 0; --i)
-    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_lines[fwd[i]]), dim3(kFftWave), 0, st, d, fwd[i], 1, 0);
-  hipLaunchKernelGGL(k_pme_gather<N>, dim3(kPmeParts, d.n_reps), dim3(kPmeBlk), 0, st, d, pos, schedule, fscale);
+    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[fwd[i]]), dim3(kPmeBlk), 0, st, d, fwd[i], 1, 0);
+  hipLaunchKernelGGL(k_pme_gather<N>, dim3(d.sc_cap), dim3(kPmeBlk), 0, st, d, pos, fscale);
   return hipGetLastError();
 }
 
@@ -461,6 +665,11 @@ hipError_t launch_pme(const Dev& d, hipStream_t st, const double* pos, int sched
     case 6: return launch_pme_order<6>(d, st, pos, schedule, fs);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_pme_init(const Dev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_pme_init, dim3(256), dim3(kPmeBlk), 0, st, d);
+  return hipGetLastError();
 }
 
 }  // namespace anb

@@ -1057,7 +1057,28 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
              (unsigned int)(kRedChunks - 1);
     }
     __syncthreads();
-    if (!last || threadIdx.x != 0) return;
+    if (!last) return;
+    // PME partial sums of the box: one slot per thread, a butterfly per
+    // wave, the waves in order (the whole block of the box's last chunk)
+    __shared__ double pme_red[kBlk / 64][PME_NPART];
+    double pme_e[PME_NPART];
+    if (d.pme_box) {
+      static_assert(kPmeParts == kBlk, "one partial-sum slot per thread");
+      const double* pp = d.pme_part + ((size_t)k * kPmeParts + threadIdx.x) * PME_NPART;
+#pragma unroll
+      for (int j = 0; j < PME_NPART; ++j) pme_e[j] = wave_sum(pp[j]);
+      if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int j = 0; j < PME_NPART; ++j) pme_red[threadIdx.x >> 6][j] = pme_e[j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < PME_NPART; ++j) {
+        double t = pme_red[0][j];
+        for (int w = 1; w < kBlk / 64; ++w) t += pme_red[w][j];
+        pme_e[j] = t;
+      }
+    }
+    if (threadIdx.x != 0) return;
     d.red_done[k] = 0u;
     double a[NACC] = {0, 0, 0, 0, 0, 0};
     for (int q = 0; q < kRedChunks; ++q)
@@ -1076,20 +1097,18 @@ __global__ void __launch_bounds__(kBlk) k_finalize(Dev d, int schedule, double i
       t[4] = a0 + a1; t[5] = a2; t[6] = L.a[2] * a0 + L.a[3] * a2; t[7] = L.a[2] * a1;
     }
     if (d.pme_box) {
-      // PME parts of the box: partial sums in slot order, then the
+      // PME parts of the box (summed above), its self energies, then the
       // background part from the group charges; S-S and W-W join the
       // lambda-independent terms, the S-W part X is scaled like the
       // solute-solvent Coulomb pairs
-      double e[PME_NPART];
-      for (int j = 0; j < PME_NPART; ++j) e[j] = 0.0;
-      const double* pp = d.pme_part + (size_t)k * kPmeParts * PME_NPART;
-      for (int q = 0; q < kPmeParts; ++q)
-        for (int j = 0; j < PME_NPART; ++j) e[j] += pp[q * PME_NPART + j];
+      const double* e = pme_e;
       const PmeBox B = d.pme_box[k];
       const double bg = -kKe * M_PI / (B.L[0] * B.L[1] * B.L[2] * d.pme_alpha * d.pme_alpha);
-      const double ss = (e[PME_E_SS] + e[PME_C_SS]) + 0.5 * bg * e[PME_Q_S] * e[PME_Q_S];
-      const double ww = (e[PME_E_WW] + e[PME_C_WW]) + 0.5 * bg * e[PME_Q_W] * e[PME_Q_W];
-      const double X = (e[PME_E_SW] + e[PME_C_SW]) + bg * e[PME_Q_S] * e[PME_Q_W];
+      const double* kc = d.pme_const + 4 * (size_t)k;
+      const double qs = kc[PME_K_Q_S], qw = kc[PME_K_Q_W];
+      const double ss = ((e[PME_E_SS] + e[PME_C_SS]) + kc[PME_K_SELF_S]) + 0.5 * bg * qs * qs;
+      const double ww = ((e[PME_E_WW] + e[PME_C_WW]) + kc[PME_K_SELF_W]) + 0.5 * bg * qw * qw;
+      const double X = (e[PME_E_SW] + e[PME_C_SW]) + bg * qs * qw;
       t[0] += ww;
       t[1] += ss;
       if (schedule == 0) {
