@@ -11,20 +11,22 @@
 //                   super-cluster: its atoms' n^3 points each are summed in an
 //                   LDS sub-grid, then added to the grid with one atomic per
 //                   point (integer sums: bit-identical from run to run);
-//   k_pme_corr      the excluded pairs' -k_e q q erf(a r)/r, one thread per
-//                   pair (the self and charge parts are constants of the
-//                   binding);
-//   forward FFT     of Z = Q_S + i Q_W along z, y, then x: a block per tile of
-//                   up to 16 adjacent lines in LDS (the first pass reads and
-//                   clears the integer grids), mixed-radix Stockham passes
-//                   (radices 5, 4, 3, 2);
-//   k_pme_convolve  splits the spectrum into those of Q_S and Q_W through
-//                   Z(-m) = conj, multiplies by the influence function C(m)
-//                   (a table written at bind), sums the S-S, W-W and S-W
-//                   energies and writes G_S + i G_W with G_S = C (S + c W),
-//                   G_W = C (W + c S);
-//   inverse FFT     the grid then holds the potentials dU/dQ_S (real part)
-//                   and dU/dQ_W (imaginary part);
+//                   further blocks take the excluded pairs' -k_e q q
+//                   erf(a r)/r, one thread per pair (the self and charge
+//                   parts are constants of the binding);
+//   k_pme_fft x2    forward transforms of Z = Q_S + i Q_W along z, then y: a
+//                   block per tile of up to 16 adjacent lines in LDS (the z
+//                   pass reads and clears the integer grids); mixed-radix
+//                   Stockham passes (radices 5, 4, 3, 2);
+//   k_pme_xconv     per tile of x-lines with their mirror lines: forward
+//                   transforms along x, the convolution (spectra of Q_S and
+//                   Q_W through Z(-m) = conj, the influence function C(m),
+//                   the S-S, W-W and S-W energies, G_S + i G_W with
+//                   G_S = C (S + c W), G_W = C (W + c S)), inverse transforms
+//                   along x;
+//   k_pme_fft x2    inverse transforms along y, then z: the grid then holds
+//                   the potentials dU/dQ_S (real part) and dU/dQ_W
+//                   (imaginary part);
 //   k_pme_gather    one block per super-cluster: its sub-grid of the
 //                   potential staged in LDS, four threads per atom summing
 //                   -q grad(sum_k M M M G) into the fixed-point force sums.
@@ -129,13 +131,11 @@ __device__ inline void block_sums(double (&v)[V], double (*red)[V]) {
 
 // ---------------------------------------------------------------- spreading
 
-// Block (part, box): the excluded pairs of the box in kPmeParts equal runs,
-// one thread per pair: -k_e q_i q_j erf(a r)/r by minimum image and its
-// forces (the S-W pairs' scaled by c).  Partial sums into the part's slots.
-__global__ void __launch_bounds__(kPmeBlk) k_pme_corr(Dev d, const double* __restrict__ xin, int schedule,
-                                                      double fscale) {
-  __shared__ double red[kPmeBlk / 64][3];
-  const int k = blockIdx.y, part = blockIdx.x;
+// Part `part` of box k's excluded pairs (kPmeParts equal runs), one thread
+// per pair: -k_e q_i q_j erf(a r)/r by minimum image and its forces (the
+// S-W pairs' scaled by c).  Partial sums into the part's slots.
+__device__ inline void pme_corr(const Dev& d, const double* __restrict__ xin, int schedule, double fscale, int k,
+                                int part, double (*red)[3]) {
   const PmeBox B = d.pme_box[k];
   const int p0 = B.pair0 + (int)((long long)B.npair * part / kPmeParts);
   const int p1 = B.pair0 + (int)((long long)B.npair * (part + 1) / kPmeParts);
@@ -279,11 +279,19 @@ __device__ inline long long sub_to_grid(const ScSub& S, const PmeBox& B, int u0,
   return ((long long)g[0] * B.n[1] + g[1]) * B.n[2] + g[2];
 }
 
-// The spreading of super-cluster blockIdx.x: LDS sub-grid, then one global
-// atomic per non-zero point (straight global atomics when the sub-grid is
-// too large).
+// Blocks [0, sc_cap): the spreading of super-cluster blockIdx.x: LDS
+// sub-grid, then one global atomic per non-zero point (straight global
+// atomics when the sub-grid is too large).  Blocks beyond: the excluded
+// pairs, part (b - sc_cap) % kPmeParts of box (b - sc_cap) / kPmeParts.
 template <int N>
-__global__ void __launch_bounds__(kPmeBlk) k_pme_spread(Dev d, const double* __restrict__ xin) {
+__global__ void __launch_bounds__(kPmeBlk) k_pme_spread(Dev d, const double* __restrict__ xin, int schedule,
+                                                        double fscale) {
+  if ((int)blockIdx.x >= d.sc_cap) {  // the excluded-pair blocks
+    __shared__ double red[kPmeBlk / 64][3];
+    const int job = (int)blockIdx.x - d.sc_cap;
+    pme_corr(d, xin, schedule, fscale, job / kPmeParts, job % kPmeParts, red);
+    return;
+  }
   __shared__ int s_atom[kSc];
   __shared__ int s_off[kSc][3];
   __shared__ double s_th[kSc][3][N], s_dth[kSc][3][N];
@@ -518,39 +526,101 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_init(Dev d) {
 
 // ------------------------------------------------------------- convolution
 
-// Block (part, box): points [P part/kPmeParts, P (part+1)/kPmeParts) of the
-// box; each point m with its partner -m handled by the smaller index.
-__global__ void __launch_bounds__(kPmeBlk) k_pme_convolve(Dev d, int schedule) {
+// The x-lines (iy, iz) of a box not after their mirror line
+// ((-iy) mod n1, (-iz) mod n2) in the order iy n2 + iz: every iz of the rows
+// 1 .. (n1-1)/2, then iz <= n2/2 of row 0 and (n1 even) of row n1/2.
+__device__ inline void canon_line(int q, int n1, int n2, int& iy, int& iz) {
+  const int A = ((n1 - 1) / 2) * n2;
+  if (q < A) {
+    iy = 1 + q / n2;
+    iz = q - (iy - 1) * n2;
+    return;
+  }
+  const int r = q - A, h = n2 / 2 + 1;
+  iy = r < h ? 0 : n1 / 2;
+  iz = r < h ? r : r - h;
+}
+
+// Block (part, box): tiles part, part + kPmeParts, ... of the box's
+// canonical x-lines, each tile holding T'(n0) of them with their mirror
+// lines in LDS: the forward transforms along x, then for each point m of a
+// canonical line with its partner -m on the mirror line (or on the same
+// line), the spectra of Q_S and Q_W (Z(-m) = conj), the influence function
+// C(m) (table), the S-S, W-W and S-W energies, and G_S + i G_W with
+// G_S = C (S + c W), G_W = C (W + c S); then the inverse transforms along x
+// and the lines back to HBM.
+__global__ void __launch_bounds__(kPmeBlk) k_pme_xconv(Dev d, int schedule) {
+  __shared__ double2 b0[kTilePts], b1[kTilePts], W[kPmeMaxN];
   __shared__ double red[kPmeBlk / 64][3];
   const int k = blockIdx.y, part = blockIdx.x;
   const PmeBox B = d.pme_box[k];
   const int n0 = B.n[0], n1 = B.n[1], n2 = B.n[2];
-  const long long P = (long long)n0 * n1 * n2;
-  const long long p0 = P * part / kPmeParts, p1 = P * (part + 1) / kPmeParts;
+  const int ncanon = canon_lines(n1, n2), TP = pair_tile_lines(n0);
+  const int ntiles = (ncanon + TP - 1) / TP;
   const double c = lam_c(d.lam[k], schedule);
   double2* g = d.pme_grid + B.off;
   const double* infl = d.pme_infl + B.off;
   double e[3] = {0.0, 0.0, 0.0};
-  for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
-    const int i0 = (int)(p / ((long long)n1 * n2));
-    const int r = (int)(p - (long long)i0 * n1 * n2);
-    const int i1 = r / n2, i2 = r - i1 * n2;
-    const int j0 = i0 == 0 ? 0 : n0 - i0, j1 = i1 == 0 ? 0 : n1 - i1, j2 = i2 == 0 ? 0 : n2 - i2;
-    const long long pp = ((long long)j0 * n1 + j1) * n2 + j2;
-    if (pp < p) continue;  // the partner's thread takes the pair
-    const double2 Z = g[p], Zc = g[pp];
-    const double C = infl[p];
-    // spectra of Q_S and Q_W at m (both grids are real)
-    const double2 S = make_double2(0.5 * (Z.x + Zc.x), 0.5 * (Z.y - Zc.y));
-    const double2 Wv = make_double2(0.5 * (Z.y + Zc.y), -0.5 * (Z.x - Zc.x));
-    const double mult = pp == p ? 1.0 : 2.0;
-    e[0] += mult * 0.5 * C * (S.x * S.x + S.y * S.y);
-    e[1] += mult * 0.5 * C * (Wv.x * Wv.x + Wv.y * Wv.y);
-    e[2] += mult * C * (S.x * Wv.x + S.y * Wv.y);
-    const double2 GS = make_double2(C * (S.x + c * Wv.x), C * (S.y + c * Wv.y));
-    const double2 GW = make_double2(C * (Wv.x + c * S.x), C * (Wv.y + c * S.y));
-    g[p] = make_double2(GS.x - GW.y, GS.y + GW.x);
-    if (pp != p) g[pp] = make_double2(GS.x + GW.y, GW.x - GS.y);
+  if (part < ntiles)
+    for (int j = threadIdx.x; j < n0; j += blockDim.x) W[j] = d.pme_roots[B.tab[0] + j];
+  for (int t = part; t < ntiles; t += kPmeParts) {
+    const int q0 = t * TP, nq = min(TP, ncanon - q0), np = 2 * nq * n0;
+    // slot 2i: canonical line q0 + i; slot 2i+1: its mirror line (a copy
+    // when the line is its own mirror)
+    for (int el = threadIdx.x; el < np; el += blockDim.x) {
+      const int slot = el / n0, ix = el - slot * n0;
+      int iy, iz;
+      canon_line(q0 + (slot >> 1), n1, n2, iy, iz);
+      if (slot & 1) {
+        iy = iy == 0 ? 0 : n1 - iy;
+        iz = iz == 0 ? 0 : n2 - iz;
+      }
+      b0[el] = g[((long long)ix * n1 + iy) * n2 + iz];
+    }
+    __syncthreads();
+    int src = 0;
+    fft_lines(b0, b1, src, n0, 2 * nq, n0, 1, W, false);
+    double2* Z = src ? b1 : b0;
+    for (int el = threadIdx.x; el < nq * n0; el += blockDim.x) {
+      const int i = el / n0, ix = el - i * n0;
+      int iy, iz;
+      canon_line(q0 + i, n1, n2, iy, iz);
+      const int my = iy == 0 ? 0 : n1 - iy, mz = iz == 0 ? 0 : n2 - iz;
+      const bool self_line = my == iy && mz == iz;
+      const int jx = ix == 0 ? 0 : n0 - ix;
+      if (self_line && jx < ix) continue;  // the partner point's thread takes the pair
+      const int a = 2 * i * n0 + ix;
+      const int b = (self_line ? 2 * i : 2 * i + 1) * n0 + jx;
+      const double2 z = Z[a], zc = Z[b];
+      const double C = infl[((long long)ix * n1 + iy) * n2 + iz];
+      const double2 S = make_double2(0.5 * (z.x + zc.x), 0.5 * (z.y - zc.y));
+      const double2 Wv = make_double2(0.5 * (z.y + zc.y), -0.5 * (z.x - zc.x));
+      const bool same = a == b;
+      const double mult = same ? 1.0 : 2.0;
+      e[0] += mult * 0.5 * C * (S.x * S.x + S.y * S.y);
+      e[1] += mult * 0.5 * C * (Wv.x * Wv.x + Wv.y * Wv.y);
+      e[2] += mult * C * (S.x * Wv.x + S.y * Wv.y);
+      const double2 GS = make_double2(C * (S.x + c * Wv.x), C * (S.y + c * Wv.y));
+      const double2 GW = make_double2(C * (Wv.x + c * S.x), C * (Wv.y + c * S.y));
+      Z[a] = make_double2(GS.x - GW.y, GS.y + GW.x);
+      if (!same) Z[b] = make_double2(GS.x + GW.y, GW.x - GS.y);
+    }
+    __syncthreads();
+    fft_lines(b0, b1, src, n0, 2 * nq, n0, 1, W, true);
+    const double2* res = src ? b1 : b0;
+    for (int el = threadIdx.x; el < np; el += blockDim.x) {
+      const int slot = el / n0, ix = el - slot * n0;
+      int iy, iz;
+      canon_line(q0 + (slot >> 1), n1, n2, iy, iz);
+      if (slot & 1) {
+        const int my = iy == 0 ? 0 : n1 - iy, mz = iz == 0 ? 0 : n2 - iz;
+        if (my == iy && mz == iz) continue;  // the copy of a self-mirrored line
+        iy = my;
+        iz = mz;
+      }
+      g[((long long)ix * n1 + iy) * n2 + iz] = res[el];
+    }
+    __syncthreads();
   }
   block_sums<3>(e, red);
   if (threadIdx.x == 0) {
@@ -643,14 +713,13 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_gather(Dev d, const double* __r
 template <int N>
 hipError_t launch_pme_order(const Dev& d, hipStream_t st, const double* pos, int schedule, double fscale) {
   const dim3 parts(kPmeParts, d.n_reps);
-  hipLaunchKernelGGL(k_pme_spread<N>, dim3(d.sc_cap), dim3(kPmeBlk), 0, st, d, pos);
-  hipLaunchKernelGGL(k_pme_corr, parts, dim3(kPmeBlk), 0, st, d, pos, schedule, fscale);
-  const int fwd[3] = {2, 1, 0};
-  for (int i = 0; i < 3; ++i)
-    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[fwd[i]]), dim3(kPmeBlk), 0, st, d, fwd[i], 0, i == 0 ? 1 : 0);
-  hipLaunchKernelGGL(k_pme_convolve, parts, dim3(kPmeBlk), 0, st, d, schedule);
-  for (int i = 2; i >= 0; --i)
-    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[fwd[i]]), dim3(kPmeBlk), 0, st, d, fwd[i], 1, 0);
+  hipLaunchKernelGGL(k_pme_spread<N>, dim3(d.sc_cap + kPmeParts * d.n_reps), dim3(kPmeBlk), 0, st, d, pos, schedule,
+                     fscale);
+  hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[2]), dim3(kPmeBlk), 0, st, d, 2, 0, 1);
+  hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[1]), dim3(kPmeBlk), 0, st, d, 1, 0, 0);
+  hipLaunchKernelGGL(k_pme_xconv, parts, dim3(kPmeBlk), 0, st, d, schedule);
+  hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[1]), dim3(kPmeBlk), 0, st, d, 1, 1, 0);
+  hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[2]), dim3(kPmeBlk), 0, st, d, 2, 1, 0);
   hipLaunchKernelGGL(k_pme_gather<N>, dim3(d.sc_cap), dim3(kPmeBlk), 0, st, d, pos, fscale);
   return hipGetLastError();
 }

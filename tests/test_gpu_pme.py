@@ -216,3 +216,35 @@ def test_pme_backward_position_and_lambda_gradients():
     d_q = torch.zeros(w.ff.n_types, dtype=torch.float64, device=pos.device)
     with pytest.raises(alchnb.AlchNBError):
         ctx.backward(pos, lam, g, d_charge=d_q)
+
+
+@pytest.mark.parametrize("schedule", [O.BEUTLER, O.LBF], ids=["beutler", "lbf"])
+def test_cross_group_exclusions_dsf_and_pme(schedule):
+    """Exclusions between solute and solvent atoms (besides solvent-solvent
+    ones): the short-range pass skips them and PME scales their reciprocal
+    correction by c(lambda) with the other solute-solvent parts; DSF and PME
+    contexts, FP64, against the oracles at two lambdas."""
+    from paper_2608_12691_amd import alchnb
+    rng = np.random.Generator(np.random.PCG64(2718))
+    w1 = workload(1)
+    s = _ortho_box(rng, 600, (21.0, 23.0, 25.0), 8, w1.ff.n_types)
+    ex = sorted({(0, 20), (1, 21), (2, 3), (3, 40), (30, 31), (30, 32), (55, 70)})
+    s.exclusions = np.array(ex, np.int32)
+    w = S.Workload(name="xexcl", systems=[s], ff=w1.ff, cutoff=9.0, skin=1.0, switch_width=1.0, dsf_alpha=ALPHA,
+                   sc_alpha=0.5, lambdas=np.array([0.7]), seed=2718)
+    for lam in (0.35, 0.8):
+        # DSF
+        ctx = alchnb.Context(w.ff, w.systems, w.cutoff, w.skin, w.switch_width, 0.2, w.sc_alpha, schedule=schedule,
+                             precision=1)
+        res = to_numpy(ctx.compute_checked(ctx.positions(w.systems), ctx.lambdas([lam]), flags=1))
+        prm = O.Params(w.cutoff, w.switch_width, 0.2, w.sc_alpha, schedule)
+        r0 = O.evaluate_system(s, w.ff, prm, lam)
+        _check(res, r0, 0, s.n_atoms, 1, "dsf lam=%g" % lam)
+        ctx.close()
+        # PME
+        ctx = _ctx(w, 1, schedule)
+        res = to_numpy(ctx.compute_checked(ctx.positions(w.systems), ctx.lambdas([lam]), flags=1))
+        ref = _oracle(w, 0, lam, schedule, ctx.pme_grid(0))
+        assert ref["corr"]["e_sw"] != 0.0
+        _check(res, ref, 0, s.n_atoms, 1, "pme lam=%g" % lam)
+        ctx.close()
