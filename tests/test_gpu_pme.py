@@ -248,3 +248,25 @@ def test_cross_group_exclusions_dsf_and_pme(schedule):
         assert ref["corr"]["e_sw"] != 0.0
         _check(res, ref, 0, s.n_atoms, 1, "pme lam=%g" % lam)
         ctx.close()
+
+
+@pytest.mark.parametrize("precision", [1, 0], ids=["fp64", "fp32"])
+def test_pme_lbf_energies_are_linear_in_the_bases(precision):
+    """Eq. 4 with PME: the solute-solvent Ewald part belongs to U_A, so the
+    energy at any lambda follows from one evaluation's bases:
+    U(l2) - U(l1) = (hA(l2) - hA(l1)) U_A + (hB(l2) - hB(l1)) U_B, which is
+    what replica exchange relies on; and dU/dlambda = hA' U_A + hB' U_B."""
+    w = workload(2)
+    ctx = _ctx(w, precision, O.LBF)
+    pos = ctx.positions(w.systems)
+    rs = {}
+    for lam in (0.42, 0.77):
+        rs[lam] = to_numpy(ctx.compute_checked(pos, ctx.lambdas([lam]), flags=1))
+    t1, t2 = rs[0.42]["terms"][0], rs[0.77]["terms"][0]
+    h1, h2 = O.lbf_switches(0.42), O.lbf_switches(0.77)
+    assert t1[4] == pytest.approx(t2[4], rel=1e-12) and t1[5] == pytest.approx(t2[5], rel=1e-12)
+    want = (h2[0] - h1[0]) * t1[4] + (h2[1] - h1[1]) * t1[5]
+    scale = abs(t1[4]) + abs(t1[5])
+    assert abs((t2[8] - t1[8]) - want) <= 1e-9 * scale
+    for t, h in ((t1, h1), (t2, h2)):
+        assert t[9] == pytest.approx(h[2] * t[4] + h[3] * t[5], rel=1e-9, abs=1e-9 * scale)
