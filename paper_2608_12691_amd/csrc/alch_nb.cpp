@@ -192,6 +192,11 @@ static void lay_out(alch_nb_ctx* ctx, char* base, Dev* d) {
   d->ent_mask = cv.take<unsigned long long>(base, E * kScCl);
   d->ent_off = cv.take<double4>(base, E);
   d->units = cv.take<int4>(base, U);
+  d->wrec = cv.take<int4>(base, kMaxWaves);
+  d->wrec_u0 = cv.take<int4>(base, kMaxWaves);
+  d->wrec_jc = cv.take<int>(base, (size_t)kMaxWaves * kMaxEpu);
+  d->wrec_info = cv.take<uint32_t>(base, (size_t)kMaxWaves * kMaxEpu);
+  d->wrec_off = cv.take<double4>(base, (size_t)kMaxWaves * kMaxEpu);
   d->rep_ustart = cv.take<int>(base, K + 1);
   d->ctr = cv.take<int>(base, 16);
   d->flags = cv.take<unsigned int>(base, 1);

@@ -191,6 +191,14 @@ struct Dev {
   int* ent_isc;              // [E]
   unsigned long long* ent_mask;  // [E*8]
   int4* units;               // [U] sc, e0, e1, replica
+  // start record of each wave of the tile launch (written with the units
+  // for the launch's wave count, ctr[CTR_WAVES]): run start, run length,
+  // 1 if the run holds solute units; the run's first unit and its entries
+  int4* wrec;                // [kMaxWaves]
+  int4* wrec_u0;             // [kMaxWaves]
+  int* wrec_jc;              // [kMaxWaves*8]
+  uint32_t* wrec_info;       // [kMaxWaves*8]
+  double4* wrec_off;         // [kMaxWaves*8]
   int* rep_ustart;           // [K+1]
   int* ctr;                  // [16] counters, see CTR_*
   unsigned int* flags;       // [1] sticky flags
@@ -257,7 +265,8 @@ struct LdInit {
   double kT, mass, gamma, dt, sigma, compress, kT_s, gamma_s, de_std, de_expl;
 };
 
-enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6 };
+enum { CTR_NSC = 0, CTR_NENT = 1, CTR_NUNIT = 2, CTR_NBUILD = 3, CTR_ENT_NEED = 4, CTR_UNIT_NEED = 5, CTR_TILES = 6,
+       CTR_WAVES = 7 };
 
 constexpr int kMaxTypes = 256;  // atom types supported by the parameter-gradient pass
 

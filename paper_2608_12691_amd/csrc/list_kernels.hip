@@ -597,6 +597,42 @@ __device__ void ph_units_fill(const Dev& d) {
   }
 }
 
+// Start records of the tile launch's nw waves (equal runs of units): the
+// run, whether it holds solute units, and the first unit's header and
+// entry data, so that a wave's first loads need neither the unit count nor
+// the unit table.  One wave per record.
+__device__ void ph_wave_records(const Dev& d, int nw) {
+  const int lane = threadIdx.x & 63;
+  const int n = d.ctr[CTR_NUNIT];
+  for (int w = gwave(); w < nw; w += gwaves()) {
+    const int ub = (int)((long long)n * w / nw);
+    const int nr = (int)((long long)n * (w + 1) / nw) - ub;
+    bool sol = false;
+    for (int r = lane; r < nr; r += 64) sol = sol || (d.units[ub + r].w & kUnitSolute) != 0;
+    const bool any_sol = __ballot(sol) != 0ull;
+    const int4 U0 = nr > 0 ? d.units[ub] : make_int4(0, 0, 0, 0);
+    if (lane == 0) {
+      d.wrec[w] = make_int4(ub, nr, any_sol ? 1 : 0, 0);
+      d.wrec_u0[w] = U0;
+    }
+    if (lane < kMaxEpu) {
+      const int e = U0.y + lane;
+      int jc = 0;
+      uint32_t inf = 0u;
+      double4 off = make_double4(0.0, 0.0, 0.0, 0.0);
+      if (nr > 0 && e < U0.z) {
+        jc = d.ent_jc[e];
+        inf = d.ent_info[e];
+        off = d.ent_off[e];
+      }
+      d.wrec_jc[w * kMaxEpu + lane] = jc;
+      d.wrec_info[w * kMaxEpu + lane] = inf;
+      d.wrec_off[w * kMaxEpu + lane] = off;
+    }
+  }
+  if (gtid() == 0) d.ctr[CTR_WAVES] = nw;
+}
+
 __device__ inline bool is_excluded(const Dev& d, int a, int b) {
   const int lo = a < b ? a : b, hi = a < b ? b : a;
   int l = d.excl_start[lo], r = d.excl_start[lo + 1];
@@ -701,6 +737,10 @@ __global__ void __launch_bounds__(kBlk) k_units_fill(Dev d, int force) {
   if (!force) { GATED; }
   ph_units_fill(d);
 }
+__global__ void __launch_bounds__(kBlk) k_wave_records(Dev d, int nw, int force) {
+  if (!force && !rebuild_on(d)) return;
+  ph_wave_records(d, nw);
+}
 __global__ void __launch_bounds__(kBlk) k_masks(Dev d, double rl2) { GATED; ph_masks(d, rl2); }
 __global__ void __launch_bounds__(kBlk) k_end(Dev d) { GATED; ph_end(d); }
 #undef GATED
@@ -764,7 +804,7 @@ __device__ inline void grid_barrier(const Dev& d, unsigned int& gen, Serial seri
 // The whole list build in one launch (phases separated by grid barriers;
 // the one-block scans run inside the barriers).
 __global__ void __launch_bounds__(kBlk) k_list_fused(Dev d, const double* __restrict__ pos, double rlm, double rl2,
-                                                     int epu, int tcap) {
+                                                     int epu, int tcap, int nw) {
   if (!rebuild_on(d)) return;
   __shared__ unsigned int gen_s;
   if (threadIdx.x == 0) gen_s = __hip_atomic_load(&d.barrier[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -789,6 +829,8 @@ __global__ void __launch_bounds__(kBlk) k_list_fused(Dev d, const double* __rest
   grid_barrier(d, gen, [&] { ph_units_scan(d); });
   ph_units_fill(d);
   grid_barrier(d, gen, none);
+  ph_wave_records(d, nw);
+  grid_barrier(d, gen, none);
   ph_end(d);
 }
 
@@ -799,7 +841,7 @@ hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, do
   const double rl2 = rlm * rlm;  // masks keep the same margin; the export test is exact
   const dim3 B(kBlk);
   if (fused_blocks > 0) {
-    hipLaunchKernelGGL(k_list_fused, dim3(fused_blocks), B, 0, st, d, pos, rlm, rl2, epu, tcap);
+    hipLaunchKernelGGL(k_list_fused, dim3(fused_blocks), B, 0, st, d, pos, rlm, rl2, epu, tcap, 4 * sh.blocks);
     return hipGetLastError();
   }
   const int g_atoms = clampi((d.n_atoms + kBlk - 1) / kBlk, 1, 256);
@@ -818,6 +860,8 @@ hipError_t launch_list_build(const Dev& d, hipStream_t st, const double* pos, do
   hipLaunchKernelGGL(k_units_count, dim3(g_sc), B, 0, st, d, epu, tcap, 0);
   hipLaunchKernelGGL(k_units_scan, dim3(1), B, 0, st, d, 0);
   hipLaunchKernelGGL(k_units_fill, dim3(g_sc), B, 0, st, d, 0);
+  hipLaunchKernelGGL(k_wave_records, dim3(clampi((4 * sh.blocks + kWpb - 1) / kWpb, 1, 256)), B, 0, st, d,
+                     4 * sh.blocks, 0);
   hipLaunchKernelGGL(k_end, dim3(1), dim3(64), 0, st, d);
   return hipGetLastError();
 }
@@ -835,6 +879,8 @@ hipError_t launch_units(const Dev& d, hipStream_t st, const TileShape& sh) {
   hipLaunchKernelGGL(k_units_count, dim3(g_sc), dim3(kBlk), 0, st, d, sh.epu, sh.tiles, 1);
   hipLaunchKernelGGL(k_units_scan, dim3(1), dim3(kBlk), 0, st, d, 1);
   hipLaunchKernelGGL(k_units_fill, dim3(g_sc), dim3(kBlk), 0, st, d, 1);
+  hipLaunchKernelGGL(k_wave_records, dim3(clampi((4 * sh.blocks + kWpb - 1) / kWpb, 1, 256)), dim3(kBlk), 0, st, d,
+                     4 * sh.blocks, 1);
   return hipGetLastError();
 }
 

@@ -493,15 +493,26 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     for (int i = threadIdx.x; i < kDsfEntries; i += kBlk) dsf[i] = d.dsf32[i];
     __syncthreads();
   }
-  const int n_units = d.ctr[CTR_NUNIT];
   // Unit range of this wave: equal runs of units (the unit cuts already cap
   // each unit's tiles; runs keep a super-cluster's units on one wave).  The
   // wave index is made provably uniform: unit and entry indices then live in
-  // scalar registers.
+  // scalar registers.  The wave's start record (written with the units for
+  // this wave count) gives the run and its first unit without waiting on
+  // the unit count; for another wave count the run follows from the count.
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = gridDim.x * (kBlk / 64), w = blockIdx.x * (kBlk / 64) + wib;
-  const int ub = (int)((long long)n_units * w / nw);
-  const int nr = (int)((long long)n_units * (w + 1) / nw) - ub;
+  const int4 wrec = d.wrec[w];
+  const int4 wu0 = d.wrec_u0[w];
+  const bool rec = d.ctr[CTR_WAVES] == nw;
+  int ub, nr;
+  if (rec) {
+    ub = wrec.x;
+    nr = wrec.y;
+  } else {
+    const int n_units = d.ctr[CTR_NUNIT];
+    ub = (int)((long long)n_units * w / nw);
+    nr = (int)((long long)n_units * (w + 1) / nw) - ub;
+  }
   // i-forces of the current super-cluster, carried over consecutive units
   // of the same super-cluster; they leave when it changes: summed over jl,
   // lane (jl, il) then takes i-cluster c = jl so that lane l holds slot
@@ -556,18 +567,22 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     return make_int4(__builtin_amdgcn_readlane(hdr.x, i), __builtin_amdgcn_readlane(hdr.y, i),
                      __builtin_amdgcn_readlane(hdr.z, i), __builtin_amdgcn_readlane(hdr.w, i));
   };
-  // Solute units first, in FP64, before the FP32 state below is live; a
-  // wave left with nothing else ends here (the loop below would only load
-  // and flush an empty super-cluster)
+  // Solute units first, in FP64, before the FP32 state below is live (runs
+  // the start record marks as free of them skip this); a wave left with
+  // nothing else ends here (the loop below would only load and flush an
+  // empty super-cluster)
   if (nr > 0) load_hdrs(0);
   int n_sol = 0;
-  for (int r = 0; r < nr; ++r) {
-    if (r > 0 && (r & 63) == 0) load_hdrs(r);
-    const int4 V = header(r);
-    if (__builtin_expect((V.w & kUnitSolute) != 0, 0)) {
-      const Pot<double> P64 = load_pot64(d.pot64);
-      solute_unit<SCHED, SW, sizeof(R) == 4>(d, P64, dsf, V, ub + r, fscale, sol_lds);
-      ++n_sol;
+  const bool scan = !rec || wrec.z != 0;
+  if (scan) {
+    for (int r = 0; r < nr; ++r) {
+      if (r > 0 && (r & 63) == 0) load_hdrs(r);
+      const int4 V = header(r);
+      if (__builtin_expect((V.w & kUnitSolute) != 0, 0)) {
+        const Pot<double> P64 = load_pot64(d.pot64);
+        solute_unit<SCHED, SW, sizeof(R) == 4>(d, P64, dsf, V, ub + r, fscale, sol_lds);
+        ++n_sol;
+      }
     }
   }
   if (n_sol == nr) return;
@@ -587,13 +602,21 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   };
   bool have_next = false;
   if (nr > 0) {
-    if (nr > 64) load_hdrs(0);
-    load_entries(header(0));
+    if (nr > 64 && scan) load_hdrs(0);  // the solute pass moved on
+    if (rec) {
+      // the first unit's entry data from the start record
+      const int k = lane >> 3;
+      n_jc = d.wrec_jc[w * kMaxEpu + k];
+      n_inf = d.wrec_info[w * kMaxEpu + k];
+      n_off = d.wrec_off[w * kMaxEpu + k];
+    } else {
+      load_entries(header(0));
+    }
     have_next = true;
   }
   for (int r = 0; r < nr; ++r) {
     if (r > 0 && (r & 63) == 0) load_hdrs(r);  // past 64 units (large boxes)
-    int4 U = header(r);
+    int4 U = r == 0 && rec ? wu0 : header(r);
     const int u = ub + r;
     // a solute unit (done by the FP64 pass above) enters as an empty unit of
     // the current super-cluster: no entries, no change of super-cluster, no
@@ -608,8 +631,8 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
     const int c_jc = n_jc;
     const uint32_t c_inf = n_inf;
     const double4 c_off = n_off;
+    // the next unit's entry data is asked for once this unit's j-data is
     have_next = r + 1 < nr && ((r + 1) & 63) != 0;
-    if (have_next) load_entries(header(r + 1));
     const int s = U.x;
     const LamState lam = d.lam[unit_rep(U.w)];
     R la0, la1;
@@ -663,6 +686,7 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
         v = pos[jsl];
         q = se[jsl];
       }
+      if (have_next) load_entries(header(r + 1));
       put_pending();
       // offset of the j-cluster's image from the i-super-cluster origin
       v.x += (R)c_off.x;
