@@ -46,8 +46,16 @@ def measured_traffic(name):
     return rec.get("hbm_bytes_per_launch")
 
 
+def timing_every(K):
+    """Stride of the timed tile launches in a K-step timed region: each timed
+    launch carries two HIP events (a few microseconds of stream time), so
+    only a sample of the calls is bracketed."""
+    return max(1, min(16, K // 4))
+
+
 def run_path(ctx, traj, lams, W, K, torch, graph):
-    """Warm up W steps, time K steps; returns (elapsed_s, tile_ms_avg, out)."""
+    """Warm up W steps, time K steps; returns (elapsed_s, tile_ms_avg, out,
+    rebuilds, last pos, last lambda, timed launches)."""
     from paper_2608_12691_amd import alchnb
     dev = traj.device
     pos = traj[0].clone()
@@ -71,7 +79,7 @@ def run_path(ctx, traj, lams, W, K, torch, graph):
         step(t)
     torch.cuda.synchronize(dev)
     st0 = ctx.get_stats()
-    ctx.set_timing(not graph)
+    ctx.set_timing(not graph, every=timing_every(K))
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     for t in range(W, W + K):
@@ -82,7 +90,7 @@ def run_path(ctx, traj, lams, W, K, torch, graph):
     st1 = ctx.get_stats()
     n_t = st1["tile_launches_timed"] - st0["tile_launches_timed"]
     tile_ms = (st1["tile_ms_total"] - st0["tile_ms_total"]) / n_t if n_t else None
-    return t1 - t0, tile_ms, out, st1["n_rebuilds"] - st0["n_rebuilds"], pos, lam
+    return t1 - t0, tile_ms, out, st1["n_rebuilds"] - st0["n_rebuilds"], pos, lam, n_t
 
 
 def count_pairs(ctx, traj, lams, W, K, torch):
@@ -172,7 +180,7 @@ def batched_vs_single(torch, steps, warmup, graph):
         lam = torch.as_tensor(np.resize(w4.lambdas, len(w.systems)), dtype=torch.float64, device=dev)
         lams = lam[None].repeat(warmup + steps, 1)
         ctx.compute_checked(traj[0].clone(), lam.clone(), flags=alchnb.FORCE_REBUILD)
-        el, tile_ms, o, rb, _, _ = run_path(ctx, traj, lams, warmup, steps, torch, graph)
+        el, tile_ms, o, rb, _, _, _ = run_path(ctx, traj, lams, warmup, steps, torch, graph)
         npairs = count_pairs(ctx, traj, lams, warmup, steps, torch)
         out[name] = dict(atoms=int(len(x0)), boxes=len(w.systems), value=npairs / el, ms_per_step=1e3 * el / steps,
                          tile_us=tile_ms * 1e3 if tile_ms else None, pairs_per_call=npairs / steps)
@@ -260,7 +268,7 @@ def pme_path(torch, w, traj, lams, W, K, dsf_ms):
     ctx = alchnb.Context(w.ff, w.systems, w.cutoff, w.skin, w.switch_width, alpha, w.sc_alpha,
                          precision=alchnb.FP32_FIXED, electrostatics=alchnb.ELEC_PME, pme_order=5, pme_spacing=1.0)
     ctx.compute_checked(traj[0].clone(), lams[0].clone(), flags=alchnb.FORCE_REBUILD)
-    elapsed, tile_ms, out, rebuilds, _, _ = run_path(ctx, traj, lams, W, K, torch, False)
+    elapsed, tile_ms, out, rebuilds, _, _, _ = run_path(ctx, traj, lams, W, K, torch, False)
     n_pairs = count_pairs(ctx, traj, lams, W, K, torch)
     flags = ctx.get_flags()
     grid = ctx.pme_grid(0)
@@ -373,7 +381,7 @@ def main():
         ctx.compute_checked(p0, lams[0].clone(), flags=alchnb.FORCE_REBUILD)
         if args.autotune:
             ctx.autotune(p0, lams[0].clone())
-        elapsed, tile_ms, out, rebuilds, pos_last, lam_last = run_path(ctx, traj, lams, W, K, torch,
+        elapsed, tile_ms, out, rebuilds, pos_last, lam_last, n_timed = run_path(ctx, traj, lams, W, K, torch,
                                                                         args.mode == "graph")
         n_pairs = count_pairs(ctx, traj, lams, W, K, torch)
         flags = ctx.get_flags()
@@ -381,7 +389,7 @@ def main():
         # final call's outputs for cross-precision errors
         ctx.compute(pos_last, lam_last, flags=alchnb.AUTO_REBUILD, out=out)
         torch.cuda.synchronize()
-        r = dict(elapsed=elapsed, tile_ms=tile_ms, n_pairs=n_pairs, rebuilds=rebuilds, flags=flags,
+        r = dict(elapsed=elapsed, tile_ms=tile_ms, n_timed=n_timed, n_pairs=n_pairs, rebuilds=rebuilds, flags=flags,
                  stats=stats, forces=out["forces"].cpu().numpy(), dudl=float(out["dudl"][0]),
                  terms=out["terms"][0].cpu().numpy())
         if prec == alchnb.FP32_FIXED:
@@ -406,6 +414,7 @@ def main():
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32, "traffic": measured_traffic("tile_fp32_water3000_traffic.json"),
                 "kernel": "k_tile<float, Beutler, switch>", "avg_launch_us": r32["tile_ms"] * 1e3,
+                "timed_launches": r32["n_timed"], "timed_every": timing_every(K),
                 "flop_per_pair": fpp, "flop_basis": "algorithmic count of the plain pair's defining formulas",
                 "pairs_per_launch": pairs_per_call,
                 "tiles_per_launch": r32["stats"]["n_tiles"],

@@ -428,8 +428,13 @@ enum { ALCH_NB_LIST_AUTO = 0, ALCH_NB_LIST_PHASES = 1, ALCH_NB_LIST_FUSED_ACTIVE
 alch_nb_status alch_nb_set_list_mode(alch_nb_ctx *ctx, int32_t mode);
 int32_t alch_nb_get_list_mode(const alch_nb_ctx *ctx);
 
-/* Tile-kernel timing with HIP events on the bound stream (on/off). */
-alch_nb_status alch_nb_set_timing(alch_nb_ctx *ctx, int32_t enable);
+/* Tile-kernel timing with HIP events on the bound stream.  every = 0: off;
+ * every = n >= 1: from now on the tile launch of every n-th call is
+ * bracketed by two events (each pair costs a few microseconds of stream
+ * time, so a sample of the calls keeps a timed run close to an untimed
+ * one).  The summed time and the count of timed launches are read with
+ * alch_nb_get_stats.  ALCH_NB_E_INVALID_ARG for every < 0. */
+alch_nb_status alch_nb_set_timing(alch_nb_ctx *ctx, int32_t every);
 
 /* Read and clear the sticky flags (synchronizes the stream). */
 alch_nb_status alch_nb_get_flags(alch_nb_ctx *ctx, uint32_t *flags);

@@ -503,8 +503,9 @@ class Context:
         self.generation += 1
         self._check("alch_nb_set_variant", self.lib.alch_nb_set_variant(self.ctx, int(v)))
 
-    def set_timing(self, on=True):
-        self._check("alch_nb_set_timing", self.lib.alch_nb_set_timing(self.ctx, int(bool(on))))
+    def set_timing(self, on=True, every=1):
+        """Time the tile launch of every `every`-th call from now on (off: on=False)."""
+        self._check("alch_nb_set_timing", self.lib.alch_nb_set_timing(self.ctx, int(every) if on else 0))
 
     def get_flags(self) -> int:
         f = ctypes.c_uint32()

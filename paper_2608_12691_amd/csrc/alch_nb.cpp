@@ -85,7 +85,8 @@ struct alch_nb_ctx {
   hipError_t last_hip = hipSuccess;
   unsigned long long* export_counter = nullptr;
   // timing
-  bool timing = false;
+  int timing_every = 0;      // tile launch of every n-th call timed (0: none)
+  long long timing_calls = 0;
   std::vector<hipEvent_t> ev;
   int n_timed = 0;
   double tile_ms = 0;
@@ -779,7 +780,8 @@ static alch_nb_status enqueue_compute(alch_nb_ctx* ctx, const double* pos, const
   hipStream_t st = ctx->stream;
   HIPCHK(launch_prepare(d, st, pos, lam, mode, 0.5 * p.skin, p.schedule));
   HIPCHK(launch_list_build(d, st, pos, ctx->r_list, sh, ctx->fused_blocks));
-  const bool timed = allow_timing && ctx->timing && ctx->n_timed < kTimingSlots;
+  const bool timed = allow_timing && ctx->timing_every > 0 && (ctx->timing_calls++ % ctx->timing_every) == 0 &&
+                     ctx->n_timed < kTimingSlots;
   if (timed) HIPCHK(hipEventRecord(ctx->ev[2 * ctx->n_timed], st));
   HIPCHK(launch_tile(d, st, ctx->pc, p.precision, p.schedule, sh, pos));
   if (timed) {
@@ -831,14 +833,15 @@ int32_t alch_nb_get_list_mode(const alch_nb_ctx* ctx) {
   return ctx->fused_blocks > 0 ? ALCH_NB_LIST_FUSED_ACTIVE : ALCH_NB_LIST_PHASES;
 }
 
-alch_nb_status alch_nb_set_timing(alch_nb_ctx* ctx, int32_t enable) {
-  if (!ctx) return ALCH_NB_E_INVALID_ARG;
-  if (enable && ctx->ev.empty()) {
+alch_nb_status alch_nb_set_timing(alch_nb_ctx* ctx, int32_t every) {
+  if (!ctx || every < 0) return ALCH_NB_E_INVALID_ARG;
+  if (every > 0 && ctx->ev.empty()) {
     // created on first use, so that binding creates no HIP objects
     ctx->ev.resize(2 * kTimingSlots);
     for (auto& e : ctx->ev) HIPCHK(hipEventCreate(&e));
   }
-  ctx->timing = enable != 0;
+  ctx->timing_every = every;
+  ctx->timing_calls = 0;
   return ALCH_NB_OK;
 }
 

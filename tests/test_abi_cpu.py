@@ -85,6 +85,9 @@ def test_create_plans_workspace(lib):
     # computing before binding is refused without touching the GPU
     assert lib.alch_nb_compute(ctx, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, None) == 6
     assert lib.alch_nb_build_list(ctx, ctypes.c_void_p(8)) == 6
+    # timing: a negative stride is refused; 0 (off) creates no HIP object
+    assert lib.alch_nb_set_timing(ctx, -1) == 1
+    assert lib.alch_nb_set_timing(ctx, 0) == 0
     lib.alch_nb_destroy(ctx)
 
 

@@ -90,6 +90,16 @@ def test_bench_frame_plan_covers_every_leg():
         b.plan_frames(5, 0, 10)
 
 
+def test_bench_times_a_sample_of_the_tile_launches():
+    """At the driver's 20 steps four launches are bracketed (every 5th);
+    at 1,000 steps every 16th; never more than every call."""
+    b = _bench_module()
+    assert b.timing_every(20) == 5
+    assert b.timing_every(1000) == 16
+    assert b.timing_every(1) == 1 and b.timing_every(3) == 1
+    assert all(1 <= b.timing_every(k) <= 16 for k in range(1, 2000))
+
+
 def test_bench_cpu_baseline_on_a_short_walk():
     """The oracle legs stay inside the frames they are given (a 25-frame walk,
     W = 5: at most 20 calls) and report both thread counts."""
