@@ -415,7 +415,9 @@ def main():
                 "frac": achieved / PEAK_FP32, "traffic": measured_traffic("tile_fp32_water3000_traffic.json"),
                 "kernel": "k_tile<float, Beutler, switch>", "avg_launch_us": r32["tile_ms"] * 1e3,
                 "timed_launches": r32["n_timed"], "timed_every": timing_every(K),
-                "flop_per_pair": fpp, "flop_basis": "algorithmic count of the plain pair's defining formulas",
+                "flop_per_pair": fpp,
+                "flop_basis": "work of a plain pair's defining formulas (erfc through an exponential), charged "
+                              "for every evaluated pair; the solute-solvent pairs' extra 30 is left out",
                 "pairs_per_launch": pairs_per_call,
                 "tiles_per_launch": r32["stats"]["n_tiles"],
                 "entries_per_launch": r32["stats"]["n_entries"],

@@ -445,7 +445,11 @@ void alch_nb_destroy(alch_nb_ctx *ctx);
 const char *alch_nb_strerror(alch_nb_status status);
 int32_t alch_nb_last_hip_error(const alch_nb_ctx *ctx);
 /* Algorithmic floating-point operations charged per evaluated pair, by
- * kind: 0 = plain pair, 1 = solute-solvent pair (used for roofline reports). */
+ * kind: 0 = plain pair (90: the work of its defining formulas, switched LJ
+ * and shifted-force electrostatics with their forces, erfc evaluated
+ * through an exponential), 1 = solute-solvent pair (120: the soft core and
+ * dU/dlambda add 30).  Used for roofline reports; independent of how a
+ * kernel computes the pair. */
 double alch_nb_flops_per_pair(int32_t kind);
 
 #ifdef __cplusplus

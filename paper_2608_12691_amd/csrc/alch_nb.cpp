@@ -316,14 +316,14 @@ const char* alch_nb_strerror(alch_nb_status s) {
 int32_t alch_nb_num_variants(void) { return kNumVariants; }
 
 double alch_nb_flops_per_pair(int32_t kind) {
-  // Algorithmic count of the pair evaluation (one add, multiply, compare,
-  // square root, exponential or error function = 1; see the design notes):
-  // displacement with image shift 6, r^2 5, cutoff test 1, 1/r, r, 1/r^2 3,
-  // combination rule 5, (sigma/r)^6 4, LJ energy and force 8, switch 15,
-  // switched LJ 4, DSF energy and force 18, force vector and both
-  // accumulations 11, energy accumulation 1 -> 81.  Solute-solvent pairs add
-  // the soft core (x, its derivatives, dU/dlambda): 24.
-  return kind == 0 ? 81.0 : 105.0;
+  // Work of the defining formulas of one pair, charged per evaluated pair
+  // whatever the kernel does to compute them: r^2 5, 1/sqrt(r^2) and r 2,
+  // combination rule 3, LJ energy and force 15, switch and its derivative
+  // 18, DSF energy and force with erfc evaluated through an exponential 30,
+  // force vector and its accumulation 12, energy 2 (87, charged as 90).
+  // Solute-solvent pairs add the soft core (x, one reciprocal, dU/dlambda):
+  // 30.
+  return kind == 0 ? 90.0 : 120.0;
 }
 
 alch_nb_status alch_nb_opes_layout(int32_t* offsets, int32_t n) {
