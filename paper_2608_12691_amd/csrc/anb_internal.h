@@ -118,17 +118,19 @@ struct PmePair {
 };
 // x-lines of a box that come before their mirror line (-iy, -iz) or are
 // their own mirror, and how many of them (each with its mirror) a tile of
-// the fused x pass holds (<= 1024 points)
+// the fused x pass holds (about 256 points a side: tiles of a few hundred
+// points give these latency-bound passes more blocks; measured on a 45^3
+// grid, 4-5 lines beat 2 and 8-16)
 __host__ __device__ inline int canon_lines(int n1, int n2) {
   return ((n1 - 1) / 2) * n2 + (n2 / 2 + 1) * (n1 % 2 == 0 ? 2 : 1);
 }
 __host__ __device__ inline int pair_tile_lines(int n0) {
-  const int t = 512 / n0;
+  const int t = 256 / n0;
   return t < 1 ? 1 : (t > 8 ? 8 : t);
 }
-// lines of an FFT tile along an axis of n points (tile of <= 1024 points)
+// lines of an FFT tile along an axis of n points (about 256 points)
 __host__ __device__ inline int tile_lines(int n) {
-  const int t = 1024 / n;
+  const int t = 256 / n;
   return t < 1 ? 1 : (t > 16 ? 16 : t);
 }
 
