@@ -267,16 +267,34 @@ __device__ inline void sc_setup(const Dev& d, const double* __restrict__ xin, in
   __syncthreads();
 }
 
+// v mod n for the sub-grid coordinates here, which lie within (-n, 2n): a
+// compare and an add (a remainder only outside that range)
+__device__ inline int wrap_n(int v, int n) {
+  if (v < 0) v += n;
+  else if (v >= n) v -= n;
+  if (v < 0 || v >= n) {
+    v %= n;
+    if (v < 0) v += n;
+  }
+  return v;
+}
+
 // Global grid index of sub-grid point (u0, u1, u2).
 __device__ inline long long sub_to_grid(const ScSub& S, const PmeBox& B, int u0, int u1, int u2) {
-  int g[3];
-  const int u[3] = {u0, u1, u2};
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    int v = (S.ref[c] + S.lo[c] + u[c]) % B.n[c];
-    g[c] = v < 0 ? v + B.n[c] : v;
-  }
-  return ((long long)g[0] * B.n[1] + g[1]) * B.n[2] + g[2];
+  const int g0 = wrap_n(S.ref[0] + S.lo[0] + u0, B.n[0]);
+  const int g1 = wrap_n(S.ref[1] + S.lo[1] + u1, B.n[1]);
+  const int g2 = wrap_n(S.ref[2] + S.lo[2] + u2, B.n[2]);
+  return ((long long)g0 * B.n[1] + g1) * B.n[2] + g2;
+}
+
+// The sub-grid walked by planes: point p = u1 e2 + u2 of the (u1, u2)
+// plane has grid offset po within an x-plane and starts at x-plane g0 (the
+// walk then steps u0 and wraps g0).
+__device__ inline void sub_plane(const ScSub& S, const PmeBox& B, int p, long long& po, int& g0) {
+  const int e2 = S.ext[2];
+  const int u1 = p / e2, u2 = p - u1 * e2;
+  po = (long long)wrap_n(S.ref[1] + S.lo[1] + u1, B.n[1]) * B.n[2] + wrap_n(S.ref[2] + S.lo[2] + u2, B.n[2]);
+  g0 = wrap_n(S.ref[0] + S.lo[0], B.n[0]);
 }
 
 // Blocks [0, sc_cap): the spreading of super-cluster blockIdx.x: LDS
@@ -327,12 +345,19 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_spread(Dev d, const double* __r
   }
   if (!lds) return;
   __syncthreads();
-  for (int e = threadIdx.x; e < S.size; e += blockDim.x) {
-    const unsigned long long v = sub[e];
-    if (v == 0ull) continue;
-    const int u0 = e / (e1 * e2), r = e - u0 * (e1 * e2);
-    const int u1 = r / e2, u2 = r - u1 * e2;
-    atomicAdd(grid + sub_to_grid(S, B, u0, u1, u2), v);
+  // one global atomic per non-zero point, walked by planes (thread: a point
+  // of the (u1, u2) plane, all its u0)
+  const int plane = e1 * e2;
+  const long long st0 = (long long)B.n[1] * B.n[2];
+  for (int p = threadIdx.x; p < plane; p += blockDim.x) {
+    long long po;
+    int g0;
+    sub_plane(S, B, p, po, g0);
+    for (int u0 = 0; u0 < S.ext[0]; ++u0) {
+      const unsigned long long v = sub[u0 * plane + p];
+      if (v != 0ull) atomicAdd(grid + g0 * st0 + po, v);
+      g0 = g0 + 1 == B.n[0] ? 0 : g0 + 1;
+    }
   }
 }
 
@@ -655,11 +680,30 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_gather(Dev d, const double* __r
   const int e1 = S.ext[1], e2 = S.ext[2];
   const double2* grid = d.pme_grid + B.off;
   if (lds) {
-    for (int e = threadIdx.x; e < S.size; e += blockDim.x) {
-      const int u0 = e / (e1 * e2), r = e - u0 * (e1 * e2);
-      const int u1 = r / e2, u2 = r - u1 * e2;
-      const double2 v = grid[sub_to_grid(S, B, u0, u1, u2)];
-      sub[e] = S.sol ? v.x : v.y;
+    // the group's potential on the sub-grid, walked by planes (thread: a
+    // point of the (u1, u2) plane, all its u0), eight loads in flight
+    const int plane = e1 * e2;
+    const long long st0 = (long long)B.n[1] * B.n[2];
+    constexpr int kBatch = 8;
+    for (int p = threadIdx.x; p < plane; p += blockDim.x) {
+      long long po;
+      int g0;
+      sub_plane(S, B, p, po, g0);
+      for (int u0 = 0; u0 < S.ext[0]; u0 += kBatch) {
+        double v[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+          v[k] = 0.0;
+          if (u0 + k < S.ext[0]) {
+            const double2 g = grid[g0 * st0 + po];
+            v[k] = S.sol ? g.x : g.y;
+          }
+          g0 = g0 + 1 == B.n[0] ? 0 : g0 + 1;
+        }
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k)
+          if (u0 + k < S.ext[0]) sub[(u0 + k) * plane + p] = v[k];
+      }
     }
     __syncthreads();
   }
