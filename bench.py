@@ -279,6 +279,26 @@ def pme_path(torch, w, traj, lams, W, K, dsf_ms):
             "spacing": 1.0, "rebuilds": rebuilds, "device_flags": flags}
 
 
+def repeat_check(ctx, pos, lam, out, torch):
+    """Run-to-run determinism: the call repeated on the same list, and two
+    calls that each rebuild the list from the same positions, compared bit
+    for bit (forces, dU/dlambda, energy terms)."""
+    from paper_2608_12691_amd import alchnb
+    keys = ("forces", "dudl", "terms")
+
+    def same(a, b):
+        return all(torch.equal(a[k], b[k]) for k in keys)
+
+    out2 = ctx.new_outputs()
+    ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out2)
+    torch.cuda.synchronize()
+    same_list = same(out, out2)
+    ctx.compute(pos, lam, flags=alchnb.FORCE_REBUILD, out=out)
+    ctx.compute(pos, lam, flags=alchnb.FORCE_REBUILD, out=out2)
+    torch.cuda.synchronize()
+    return {"same_list_bit_exact": bool(same_list), "rebuilt_list_bit_exact": bool(same(out, out2))}
+
+
 def rebuild_cost(ctx, traj, lams, torch, reps=10):
     """Extra time of a call that rebuilds the list: forced rebuilds against
     plain calls at the same positions (HIP events on the bound stream)."""
@@ -392,6 +412,10 @@ def main():
         r = dict(elapsed=elapsed, tile_ms=tile_ms, n_timed=n_timed, n_pairs=n_pairs, rebuilds=rebuilds, flags=flags,
                  stats=stats, forces=out["forces"].cpu().numpy(), dudl=float(out["dudl"][0]),
                  terms=out["terms"][0].cpu().numpy())
+        try:
+            r["repeat"] = repeat_check(ctx, pos_last, lam_last, out, torch)
+        except Exception as e:  # noqa: BLE001 - reported in the line
+            r["repeat"] = {"error": repr(e)}
         if prec == alchnb.FP32_FIXED:
             try:
                 r["rebuild_us"], r["plain_call_us"] = rebuild_cost(ctx, traj, lams, torch)
@@ -460,6 +484,7 @@ def main():
             "dudl_rel": abs(r32["dudl"] - r64["dudl"]) / max(abs(r64["dudl"]), 1e-300),
             "energy_rel": float(abs(r32["terms"][8] - r64["terms"][8]) / max(abs(r64["terms"][8]), 1e-300))}
     line["device_flags"] = {"fp32": r32["flags"], "fp64": res.get(alchnb.FP64, {}).get("flags")}
+    line["repeat"] = {"fp32": r32.get("repeat"), "fp64": res.get(alchnb.FP64, {}).get("repeat")}
     if not args.no_batched:
         optional(line, "hrex16", lambda: batched_vs_single(torch, args.batched_steps, 20, args.mode == "graph"))
     if not args.no_pme:
