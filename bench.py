@@ -49,8 +49,8 @@ def measured_traffic(name):
 def timing_every(K):
     """Stride of the timed tile launches in a K-step timed region: each timed
     launch carries two HIP events (a few microseconds of stream time), so
-    only a sample of the calls is bracketed."""
-    return max(1, min(16, K // 4))
+    only a sample of the calls is bracketed (two of a short run)."""
+    return max(1, min(16, K // 2))
 
 
 def run_path(ctx, traj, lams, W, K, torch, graph):

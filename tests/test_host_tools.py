@@ -91,10 +91,10 @@ def test_bench_frame_plan_covers_every_leg():
 
 
 def test_bench_times_a_sample_of_the_tile_launches():
-    """At the driver's 20 steps four launches are bracketed (every 5th);
+    """At the driver's 20 steps two launches are bracketed (every 10th);
     at 1,000 steps every 16th; never more than every call."""
     b = _bench_module()
-    assert b.timing_every(20) == 5
+    assert b.timing_every(20) == 10
     assert b.timing_every(1000) == 16
     assert b.timing_every(1) == 1 and b.timing_every(3) == 1
     assert all(1 <= b.timing_every(k) <= 16 for k in range(1, 2000))
