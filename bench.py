@@ -118,7 +118,30 @@ def plan_frames(W, K, cpu_calls):
     return W + max(K, cpu_calls)
 
 
-def _oracle_leg(w, traj_np, lams_np, first, max_calls, budget_s, threads):
+def errors_vs_oracle(gpu, ref):
+    """Errors of one GPU result against the oracle's for the same call:
+    forces sqrt(sum |F - F_ref|^2 / sum |F_ref|^2); dU/dlambda relative to
+    |ref|, or to S = sum over pairs of |du/dlambda| when |ref| < 1e-2 S
+    (cancellation); each energy term relative to the sum over pairs of |u|
+    for that term, the largest over the terms."""
+    import numpy as np
+    F, Fr = np.asarray(gpu["forces"]), np.asarray(ref["forces"])
+    den = float(np.sum(Fr * Fr))
+    e_f = float(np.sqrt(np.sum((F - Fr) ** 2) / den)) if den > 0 else float(np.abs(F).max())
+    scale = np.asarray(ref["abs_terms"])
+    d, dr = float(gpu["dudl"]), float(ref["terms"][9])
+    if scale[9] <= 0:
+        e_d = abs(d - dr)
+    elif abs(dr) >= 1e-2 * scale[9]:
+        e_d = abs(d - dr) / abs(dr)
+    else:
+        e_d = abs(d - dr) / scale[9]
+    t, tr = np.asarray(gpu["terms"]), np.asarray(ref["terms"])
+    e_e = max(abs(t[j] - tr[j]) / scale[j] if scale[j] > 0 else abs(t[j] - tr[j]) for j in range(len(tr)))
+    return {"force_rms_rel": e_f, "dudl_rel": e_d, "energy_rel": float(e_e)}
+
+
+def _oracle_leg(w, traj_np, lams_np, first, max_calls, budget_s, threads, keep_first=None):
     import oracle as O
     s = w.systems[0]
     P = O.Params.of(w)
@@ -127,7 +150,9 @@ def _oracle_leg(w, traj_np, lams_np, first, max_calls, budget_s, threads):
     last = min(first + max_calls, len(traj_np))
     if last <= first:
         raise ValueError("no frame left for the CPU sample (first %d, frames %d)" % (first, len(traj_np)))
-    ev(first)  # library load and cache warm-up, untimed
+    r0 = ev(first)  # library load and cache warm-up, untimed
+    if keep_first is not None:
+        keep_first.append(r0)
     n = calls = 0
     t0 = time.perf_counter()
     for t in range(first, last):
@@ -152,11 +177,15 @@ def host_threads():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(w, traj_np, lams_np, W, max_calls, budget_s=12.0, budget_1core_s=10.0):
+def cpu_baseline(w, traj_np, lams_np, W, max_calls, budget_s=12.0, budget_1core_s=10.0, gpu_first=None):
     """The oracle timed on the host: all threads, then one, each on a bounded
     sample of the calls the GPU timed (stopping at max_calls calls or once the
-    time budget is spent)."""
-    rec = _oracle_leg(w, traj_np, lams_np, W, max_calls, budget_s, host_threads())
+    time budget is spent).  gpu_first: GPU results at the sample's first call
+    by precision; their errors against the oracle's result are recorded."""
+    first = []
+    rec = _oracle_leg(w, traj_np, lams_np, W, max_calls, budget_s, host_threads(), keep_first=first)
+    if gpu_first:
+        rec["error_vs_oracle"] = {"call": W, **{k: errors_vs_oracle(v, first[0]) for k, v in gpu_first.items()}}
     try:
         rec["single_core"] = _oracle_leg(w, traj_np, lams_np, W, max_calls, budget_1core_s, 1)
     except Exception as e:  # the all-core figure stands on its own
@@ -416,6 +445,13 @@ def main():
             r["repeat"] = repeat_check(ctx, pos_last, lam_last, out, torch)
         except Exception as e:  # noqa: BLE001 - reported in the line
             r["repeat"] = {"error": repr(e)}
+        # the result at the first call the oracle times (its error is
+        # reported with the oracle's leg)
+        out_w = ctx.new_outputs()
+        ctx.compute(traj[W].clone(), lams[W].clone(), flags=alchnb.AUTO_REBUILD, out=out_w)
+        torch.cuda.synchronize()
+        r["at_first"] = dict(forces=out_w["forces"].cpu().numpy(), dudl=float(out_w["dudl"][0]),
+                             terms=out_w["terms"][0].cpu().numpy())
         if prec == alchnb.FP32_FIXED:
             try:
                 r["rebuild_us"], r["plain_call_us"] = rebuild_cost(ctx, traj, lams, torch)
@@ -492,8 +528,10 @@ def main():
     if not args.no_aux:
         optional(line, "aux", lambda: aux_paths(torch, w, traj, lams, min(W, 20), min(K, args.aux_steps)))
     if not args.no_cpu_baseline:
+        gpu_first = {("fp32" if p == alchnb.FP32_FIXED else "fp64"): r["at_first"] for p, r in res.items()
+                     if "at_first" in r}
         optional(line, "cpu_baseline", lambda: cpu_baseline(w, traj_np, lams_np, W, cpu_calls, args.cpu_seconds,
-                                                            args.cpu_seconds_1core))
+                                                            args.cpu_seconds_1core, gpu_first))
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)

@@ -117,6 +117,24 @@ def test_bench_cpu_baseline_on_a_short_walk():
     # a sample that starts past the last frame is an error, not an index fault
     with pytest.raises(ValueError):
         b._oracle_leg(w, traj, lams, W + K, 10, 1.0, 1)
+    # GPU results at the sample's first call are compared with the oracle's
+    import oracle as O
+    ref = O.evaluate(traj[W], s.types, s.is_solute, s.exclusions, s.box, w.ff.sigma, w.ff.epsilon, w.ff.charge,
+                     O.Params.of(w), lams[W])
+    exact = dict(forces=ref["forces"].copy(), dudl=ref["terms"][9], terms=ref["terms"].copy())
+    off = dict(forces=ref["forces"] * (1 + 1e-6), dudl=ref["terms"][9] + 1e-3 * ref["abs_terms"][9],
+               terms=ref["terms"] + 2e-7 * ref["abs_terms"])
+    rec = b.cpu_baseline(w, traj, lams, W, 2, budget_s=0.2, budget_1core_s=0.2,
+                         gpu_first={"fp32": off, "fp64": exact})
+    e = rec["error_vs_oracle"]
+    assert e["call"] == W
+    assert e["fp64"] == {"force_rms_rel": 0.0, "dudl_rel": 0.0, "energy_rel": 0.0}
+    assert abs(e["fp32"]["force_rms_rel"] - 1e-6) < 1e-9
+    assert abs(e["fp32"]["energy_rel"] - 2e-7) < 1e-9
+    d = abs(ref["terms"][9])
+    S = ref["abs_terms"][9]
+    want = 1e-3 * S / d if d >= 1e-2 * S else 1e-3
+    assert abs(e["fp32"]["dudl_rel"] - want) < 1e-9 * max(1.0, want)
 
 
 def test_bench_optional_leg_failure_is_recorded():
