@@ -7,8 +7,9 @@
 // Per call, after the short-range tile kernel and before the final
 // reduction:
 //   k_pme_spread    charges -> two int64 fixed-point grids (solute S,
-//                   solvent W) with order-n cardinal B-splines, one block per
-//                   super-cluster: its atoms' n^3 points each are summed in an
+//                   solvent W) with order-n cardinal B-splines, kScSplit
+//                   blocks per super-cluster, each over a part of its
+//                   slots: their atoms' n^3 points each are summed in an
 //                   LDS sub-grid, then added to the grid with one atomic per
 //                   point (integer sums: bit-identical from run to run);
 //                   further blocks take the excluded pairs' -k_e q q
@@ -27,7 +28,7 @@
 //   k_pme_fft x2    inverse transforms along y, then z: the grid then holds
 //                   the potentials dU/dQ_S (real part) and dU/dQ_W
 //                   (imaginary part);
-//   k_pme_gather    one block per super-cluster: its sub-grid of the
+//   k_pme_gather    kScSplit blocks per super-cluster: the sub-grid of the
 //                   potential staged in LDS, four threads per atom summing
 //                   -q grad(sum_k M M M G) into the fixed-point force sums.
 // Energies leave as per-box partial sums in fixed slots; the final
@@ -43,6 +44,11 @@ namespace anb {
 namespace {
 
 constexpr int kPmeBlk = 256;
+// blocks per super-cluster in spreading and gather: block part p takes the
+// slots p * 64 / kScSplit .. (p + 1) * 64 / kScSplit - 1 (more blocks than
+// compute units for these latency-bound passes)
+constexpr int kScSplit = 2;
+static_assert(kSc % kScSplit == 0, "equal slot ranges");
 constexpr int kTilePts = 1024;  // points of an FFT tile (T(n) lines of n points)
 static_assert(kPmeMaxN <= kTilePts, "a tile holds at least one line");
 
@@ -205,11 +211,12 @@ __device__ inline int wrap_half(int v, int n) {  // v in (-n, n) -> (-n/2, n/2]
 // the reference (unwrapped across the box edge) and spline weights and
 // derivatives; then the sub-grid.  All threads return the header (n = 0: empty super-cluster).
 template <int N>
-__device__ inline void sc_setup(const Dev& d, const double* __restrict__ xin, int s, int* s_atom,
+__device__ inline void sc_setup(const Dev& d, const double* __restrict__ xin, int s, int part, int* s_atom,
                                 int (*s_off)[3], double (*s_th)[3][N], double (*s_dth)[3][N], double* s_q, ScSub& S) {
   if (threadIdx.x < kSc) {
     const int l = threadIdx.x;
-    const int a = d.slot_atom[s * kSc + l];
+    // the slots of this block's part (the others are left empty)
+    const int a = l / (kSc / kScSplit) == part ? d.slot_atom[s * kSc + l] : -1;
     const unsigned long long valid = __ballot(a >= 0);
     if (valid == 0) {
       if (l == 0) S.n = 0;
@@ -297,16 +304,17 @@ __device__ inline void sub_plane(const ScSub& S, const PmeBox& B, int p, long lo
   g0 = wrap_n(S.ref[0] + S.lo[0], B.n[0]);
 }
 
-// Blocks [0, sc_cap): the spreading of super-cluster blockIdx.x: LDS
-// sub-grid, then one global atomic per non-zero point (straight global
-// atomics when the sub-grid is too large).  Blocks beyond: the excluded
-// pairs, part (b - sc_cap) % kPmeParts of box (b - sc_cap) / kPmeParts.
+// Blocks [0, S = kScSplit sc_cap): the spreading of part b % kScSplit of
+// super-cluster b / kScSplit: LDS sub-grid, then one global atomic per
+// non-zero point (straight global atomics when the sub-grid is too large).
+// Blocks beyond: the excluded pairs, part (b - S) % kPmeParts of box
+// (b - S) / kPmeParts.
 template <int N>
 __global__ void __launch_bounds__(kPmeBlk) k_pme_spread(Dev d, const double* __restrict__ xin, int schedule,
                                                         double fscale) {
-  if ((int)blockIdx.x >= d.sc_cap) {  // the excluded-pair blocks
+  if ((int)blockIdx.x >= kScSplit * d.sc_cap) {  // the excluded-pair blocks
     __shared__ double red[kPmeBlk / 64][3];
-    const int job = (int)blockIdx.x - d.sc_cap;
+    const int job = (int)blockIdx.x - kScSplit * d.sc_cap;
     pme_corr(d, xin, schedule, fscale, job / kPmeParts, job % kPmeParts, red);
     return;
   }
@@ -316,8 +324,8 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_spread(Dev d, const double* __r
   __shared__ double s_q[kSc];
   __shared__ ScSub S;
   __shared__ unsigned long long sub[kSubMax];
-  const int s = blockIdx.x;
-  sc_setup<N>(d, xin, s, s_atom, s_off, s_th, s_dth, s_q, S);
+  const int s = (int)blockIdx.x / kScSplit;
+  sc_setup<N>(d, xin, s, (int)blockIdx.x % kScSplit, s_atom, s_off, s_th, s_dth, s_q, S);
   if (S.n == 0) return;
   const PmeBox B = d.pme_box[S.k];
   const bool lds = S.size > 0;
@@ -672,8 +680,8 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_gather(Dev d, const double* __r
   __shared__ double s_q[kSc];
   __shared__ ScSub S;
   __shared__ double sub[kSubMax];
-  const int s = blockIdx.x;
-  sc_setup<N>(d, xin, s, s_atom, s_off, s_th, s_dth, s_q, S);
+  const int s = (int)blockIdx.x / kScSplit;
+  sc_setup<N>(d, xin, s, (int)blockIdx.x % kScSplit, s_atom, s_off, s_th, s_dth, s_q, S);
   if (S.n == 0) return;
   const PmeBox B = d.pme_box[S.k];
   const bool lds = S.size > 0;
@@ -757,14 +765,15 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_gather(Dev d, const double* __r
 template <int N>
 hipError_t launch_pme_order(const Dev& d, hipStream_t st, const double* pos, int schedule, double fscale) {
   const dim3 parts(kPmeParts, d.n_reps);
-  hipLaunchKernelGGL(k_pme_spread<N>, dim3(d.sc_cap + kPmeParts * d.n_reps), dim3(kPmeBlk), 0, st, d, pos, schedule,
+  hipLaunchKernelGGL(k_pme_spread<N>, dim3(kScSplit * d.sc_cap + kPmeParts * d.n_reps), dim3(kPmeBlk), 0, st, d,
+                     pos, schedule,
                      fscale);
   hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[2]), dim3(kPmeBlk), 0, st, d, 2, 0, 1);
   hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[1]), dim3(kPmeBlk), 0, st, d, 1, 0, 0);
   hipLaunchKernelGGL(k_pme_xconv, parts, dim3(kPmeBlk), 0, st, d, schedule);
   hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[1]), dim3(kPmeBlk), 0, st, d, 1, 1, 0);
   hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[2]), dim3(kPmeBlk), 0, st, d, 2, 1, 0);
-  hipLaunchKernelGGL(k_pme_gather<N>, dim3(d.sc_cap), dim3(kPmeBlk), 0, st, d, pos, fscale);
+  hipLaunchKernelGGL(k_pme_gather<N>, dim3(kScSplit * d.sc_cap), dim3(kPmeBlk), 0, st, d, pos, fscale);
   return hipGetLastError();
 }
 
