@@ -219,6 +219,106 @@ def batched_vs_single(torch, steps, warmup, graph):
     return out
 
 
+# physical constants of the dynamics legs
+KB_KCAL = 0.0019872042586408316  # kcal/(mol K)
+DA_NM2 = 1.0e6 / 4.184           # 1 Da nm^2 in kcal/mol fs^2
+
+
+def _paired_ms(torch, step, W, K):
+    """ms per step of step(t, extra) with and without the extra work, each
+    over K steps after W warm-up steps (HIP events on the current stream)."""
+    res = []
+    for extra in (False, True):
+        for t in range(W):
+            step(t, extra)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for t in range(W, W + K):
+            step(t, extra)
+        e1.record()
+        torch.cuda.synchronize()
+        res.append(e0.elapsed_time(e1) / K)
+    return res
+
+
+def dynamics_path(torch, w, traj, lams, W, K):
+    """lambda-OPES-d-AFED per step on the timed walk (FP32, LBF schedule):
+    the evaluation at the current lambda, 4 dihedral CVs of the solute
+    coupled to their s_k (eq. 15), and one theta / s_k step (dual OPES,
+    kernels every 400 steps, TI bins) that writes the next lambda; timed
+    against the same evaluations at a fixed lambda."""
+    import numpy as np
+    from paper_2608_12691_amd import alchnb
+    s = w.systems[0]
+    dev = traj.device
+    ctx = alchnb.from_workload(w, precision=alchnb.FP32_FIXED, schedule=alchnb.LBF_DSF)
+    ctx.compute_checked(traj[0].clone(), lams[0].clone(), flags=alchnb.FORCE_REBUILD)
+    n_cv = 4
+    sol = np.nonzero(s.is_solute)[0]
+    idx = torch.tensor(sol[:16].reshape(n_cv, 4), dtype=torch.int32, device=dev)
+    prm = dict(capacity=96, stride=400, ti_bins=10, n_cv=n_cv, kT=KB_KCAL * 298.0, mass=DA_NM2, friction=0.025,
+               dt=1.0, sigma=0.10, barrier_std=30.0, barrier_expl=5.0, compress=1.0, kT_s=KB_KCAL * 1000.0,
+               friction_s=0.025)
+    state, lay = ctx.ld_init(prm, [0.5], s0=[0.0] * n_cv, mass_s=[50.0 * DA_NM2] * n_cv, kappa=[239.0] * n_cv)
+    s_view = state[lay["cv_s"]:lay["cv_s"] + n_cv]
+    kap = torch.full((n_cv,), 239.0, dtype=torch.float64, device=dev)
+    rng = np.random.Generator(np.random.PCG64(2608))
+    noise = torch.as_tensor(rng.standard_normal((1024, 1 + n_cv)), device=dev)
+    lam = lams[0].clone()
+    out = ctx.new_outputs()
+    cv = ctx.dihedrals(traj[0], idx, s=s_view, kappa=kap)
+
+    def step(t, extra):
+        ctx.compute(traj[t], lam, flags=alchnb.AUTO_REBUILD, out=out)
+        if extra:
+            ctx.dihedrals(traj[t], idx, s=s_view, kappa=kap, forces=out["forces"], out=cv)
+            ctx.ld_step(state, out["dudl"], noise, lam, xi=cv["xi"])
+
+    plain, dyn = _paired_ms(torch, step, W, K)
+    flags = ctx.get_flags()
+    rec = {"ms_per_step": dyn, "evaluation_ms_per_step": plain, "dynamics_us_per_step": 1e3 * (dyn - plain),
+           "steps": K, "n_cv": n_cv, "deposition_stride": prm["stride"], "lambda_final": float(lam[0]),
+           "device_flags": flags}
+    ctx.close()
+    return rec
+
+
+def hrex_path(torch, steps, warmup):
+    """One exchange attempt per evaluation of the 16 boxes at lambda_k = k/15
+    (FP32, LBF schedule: swaps decided from the basis energies, eq. 4), timed
+    against the evaluations alone."""
+    import numpy as np
+    from paper_2608_12691_amd import alchnb, systems
+    w4 = systems.make_config(4)
+    K = len(w4.systems)
+    dev = torch.device("cuda:0")
+    ctx = alchnb.from_workload(w4, precision=alchnb.FP32_FIXED, schedule=alchnb.LBF_DSF)
+    pos = ctx.positions(w4.systems)
+    states = np.asarray(w4.lambdas, float)
+    lam = ctx.lambdas(states)
+    out = ctx.new_outputs()
+    ls = torch.as_tensor(states, device=dev)
+    rng = np.random.Generator(np.random.PCG64(1515))
+    uu = torch.as_tensor(rng.uniform(0.0, 1.0, (256, K - 1)), device=dev)
+    ctx.compute_checked(pos, lam, flags=alchnb.FORCE_REBUILD, out=out)
+    so, stats = ctx.hrex_init()
+    kT = KB_KCAL * 298.0
+
+    def step(t, extra):
+        ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
+        if extra:
+            ctx.hrex_exchange(out["terms"], ls, so, lam, uu, kT, stats)
+
+    plain, ex = _paired_ms(torch, step, warmup, steps)
+    st = stats.cpu().numpy()
+    rec = {"ms_per_step": ex, "evaluation_ms_per_step": plain, "attempt_us": 1e3 * (ex - plain), "boxes": K,
+           "attempts": int(st[0]), "pair_attempts": int(st[1:K].sum()), "pair_accepts": int(st[K:].sum()),
+           "device_flags": ctx.get_flags()}
+    ctx.close()
+    return rec
+
+
 def aux_paths(torch, w, traj, lams, W, K):
     """The rows beside the forward, on the same walk and the FP32 path: the
     backward for the Cartesian and lambda gradients, the backward with the
@@ -393,6 +493,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200)
     ap.add_argument("--no-pme", action="store_true")
     ap.add_argument("--no-aux", action="store_true")
+    ap.add_argument("--no-dynamics", action="store_true", help="skip the lambda-dynamics and exchange legs")
     ap.add_argument("--aux-steps", type=int, default=300)
     ap.add_argument("--rebuild-calls", type=int, default=1000, help="walk length for the calls-per-rebuild figure")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -527,6 +628,9 @@ def main():
         optional(line, "pme", lambda: pme_path(torch, w, traj, lams, W, K, line["ms_per_step"]))
     if not args.no_aux:
         optional(line, "aux", lambda: aux_paths(torch, w, traj, lams, min(W, 20), min(K, args.aux_steps)))
+    if not args.no_dynamics:
+        optional(line, "dynamics", lambda: dynamics_path(torch, w, traj, lams, min(W, 20), min(K, args.aux_steps)))
+        optional(line, "hrex_exchange", lambda: hrex_path(torch, min(K, 100), min(W, 10)))
     if not args.no_cpu_baseline:
         gpu_first = {("fp32" if p == alchnb.FP32_FIXED else "fp64"): r["at_first"] for p, r in res.items()
                      if "at_first" in r}
