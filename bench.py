@@ -286,8 +286,9 @@ def dynamics_path(torch, w, traj, lams, W, K):
 
 def hrex_path(torch, steps, warmup):
     """One exchange attempt per evaluation of the 16 boxes at lambda_k = k/15
-    (FP32, LBF schedule: swaps decided from the basis energies, eq. 4), timed
-    against the evaluations alone."""
+    (FP32, LBF schedule: swaps decided from the basis energies, eq. 4): each
+    attempt bracketed by HIP events (it is small beside the evaluation, so a
+    difference of two timed loops would not resolve it)."""
     import numpy as np
     from paper_2608_12691_amd import alchnb, systems
     w4 = systems.make_config(4)
@@ -304,15 +305,24 @@ def hrex_path(torch, steps, warmup):
     ctx.compute_checked(pos, lam, flags=alchnb.FORCE_REBUILD, out=out)
     so, stats = ctx.hrex_init()
     kT = KB_KCAL * 298.0
-
-    def step(t, extra):
+    for _ in range(warmup):
         ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
-        if extra:
-            ctx.hrex_exchange(out["terms"], ls, so, lam, uu, kT, stats)
-
-    plain, ex = _paired_ms(torch, step, warmup, steps)
+        ctx.hrex_exchange(out["terms"], ls, so, lam, uu, kT, stats)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for a, b in ev:
+        ctx.compute(pos, lam, flags=alchnb.AUTO_REBUILD, out=out)
+        a.record()
+        ctx.hrex_exchange(out["terms"], ls, so, lam, uu, kT, stats)
+        b.record()
+    t1.record()
+    torch.cuda.synchronize()
+    attempt_ms = sum(a.elapsed_time(b) for a, b in ev) / steps
     st = stats.cpu().numpy()
-    rec = {"ms_per_step": ex, "evaluation_ms_per_step": plain, "attempt_us": 1e3 * (ex - plain), "boxes": K,
+    rec = {"attempt_us": 1e3 * attempt_ms, "step_ms_with_events": t0.elapsed_time(t1) / steps, "boxes": K,
            "attempts": int(st[0]), "pair_attempts": int(st[1:K].sum()), "pair_accepts": int(st[K:].sum()),
            "device_flags": ctx.get_flags()}
     ctx.close()
