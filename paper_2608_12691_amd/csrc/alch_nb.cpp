@@ -622,21 +622,30 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
   // intervals per unit of r: the largest power of two with rc * inv_h <= kDsfN,
   // so that r * inv_h and its fraction are exact in FP32
   pc.inv_h = std::exp2(std::floor(std::log2(kDsfN / p.cutoff)));
-  // cubic Hermite pieces of f(r) = erfc(a r) and g(r) = (2a/sqrt(pi)) exp(-a^2 r^2)
-  // (f' = -g, g' = -2 a^2 r g) in t = (r - r0)/h: c0 + t (c1 + t (c2 + t c3))
+  // cubic Hermite pieces, in t = (r - r0)/h as c0 + t (c1 + t (c2 + t c3)),
+  // of the smooth factors the FP32 pair math multiplies by q q / r: with
+  // f(r) = erfc(a r) and g(r) = (2a/sqrt(pi)) exp(-a^2 r^2) (f' = -g,
+  // g' = -2 a^2 r g),
+  //   T1(r) = r D(r)          = f - A r + B r (r - rc),  T1' = -g - A + B (2r - rc)
+  //   T2(r) = r (-r dD/dr)    = f + r g - B r^2,          T2' = -2 a^2 r^2 g - 2 B r
+  // (the shift's cancellation near rc is done here in FP64)
   ctx->dsf32.resize(kDsfEntries);
   {
-    const double a = p.dsf_alpha, h = 1.0 / pc.inv_h;
+    const double a = p.dsf_alpha, h = 1.0 / pc.inv_h, A = pc.A, B = pc.B, rc = pc.rc;
     auto f = [&](double r) { return std::erfc(a * r); };
     auto g = [&](double r) { return pc.c2a * std::exp(-a * a * r * r); };
+    auto t1 = [&](double r) { return f(r) - A * r + B * r * (r - rc); };
+    auto d1 = [&](double r) { return -g(r) - A + B * (2.0 * r - rc); };
+    auto t2 = [&](double r) { return f(r) + r * g(r) - B * r * r; };
+    auto d2 = [&](double r) { return -2.0 * a * a * r * r * g(r) - 2.0 * B * r; };
     auto piece = [&](double y0, double y1, double d0, double d1) {
       return make_float4((float)y0, (float)(h * d0), (float)(3.0 * (y1 - y0) - h * (2.0 * d0 + d1)),
                          (float)(2.0 * (y0 - y1) + h * (d0 + d1)));
     };
     for (int i = 0; i <= kDsfN; ++i) {
       const double r0 = i * h, r1 = r0 + h;
-      ctx->dsf32[2 * i] = piece(f(r0), f(r1), -g(r0), -g(r1));
-      ctx->dsf32[2 * i + 1] = piece(g(r0), g(r1), -2.0 * a * a * r0 * g(r0), -2.0 * a * a * r1 * g(r1));
+      ctx->dsf32[2 * i] = piece(t1(r0), t1(r1), d1(r0), d1(r1));
+      ctx->dsf32[2 * i + 1] = piece(t2(r0), t2(r1), d2(r0), d2(r1));
     }
   }
   // type-pair table in FP64: sigma_ij, 4 eps_ij, k_e q_i q_j, 1/sigma_ij^6

@@ -217,7 +217,7 @@ struct Dev {
   double* last_dudl;         // [K] dU/dlambda of the last forward
   unsigned long long* pg_fix;  // [3][SC*64] parameter-gradient sums per slot (fixed point), cleared after each pass
   const float4* tp32;        // [T*T] type-pair sigma, 4 eps, k_e q q, 1/sigma^6 (rounded from FP64)
-  const float4* dsf32;       // [kDsfEntries] FP32 DSF pieces (erfc, then the Gaussian term, per interval)
+  const float4* dsf32;       // [kDsfEntries] FP32 pieces of r D(r), then r (-r dD/dr), per interval
   const double4* tp64;       // [T*T]
   const double* pot64;       // [kPot64Words] FP64 potential constants of the solute units (see pot64_words)
   // PME (pme_box == nullptr: DSF electrostatics)

@@ -17,10 +17,11 @@ struct PotConsts {
   double inv_h;                // intervals per unit of r in the FP32 DSF table (a power of two)
 };
 
-// The FP32 path reads erfc(a r) and (2a/sqrt(pi)) exp(-a^2 r^2) from cubic
-// Hermite pieces on kDsfN + 1 equal intervals of width 1/inv_h starting at
-// r = 0, with rc * inv_h <= kDsfN; each interval holds two float4 of
-// coefficients in the local variable t in [0, 1].
+// The FP32 path reads r D(r) and r (-r dD/dr) (D the electrostatic pair
+// function, shift included) from cubic Hermite pieces on kDsfN + 1 equal
+// intervals of width 1/inv_h starting at r = 0, with rc * inv_h <= kDsfN;
+// each interval holds two float4 of coefficients in the local variable t
+// in [0, 1].
 constexpr int kDsfN = 256;
 constexpr int kDsfEntries = 2 * (kDsfN + 1);
 

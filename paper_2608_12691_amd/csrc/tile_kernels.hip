@@ -107,11 +107,13 @@ __host__ Pot<R> make_pot(const PotConsts& p) {
 
 // Switched LJ, DSF and the scalar pair force.  Lanes outside the cutoff or
 // masked out get r2 := 1 so every value stays finite (callers select their
-// outputs to zero or run the lanes of in-range pairs only).  erfc(a r) and
-// the Gaussian term by route E: kErfcTable, the FP32 cubic pieces in tab
-// (LDS; FP64 takes the library functions); kErfcFit, the FP32 rational fit
-// (FP64: the library); kErfcCheb, the FP64 Chebyshev series (few registers;
-// FP32 takes the rational fit).
+// outputs to zero or run the lanes of in-range pairs only).  The
+// electrostatic factors by route E: kErfcTable, the FP32 cubic pieces in tab
+// (LDS) of r D(r) and of r times -r dD/dr, smooth functions of r whose
+// shifts were formed in FP64 (FP64 takes the library functions);
+// kErfcFit, erfc and the Gaussian term from the FP32 rational fit (FP64:
+// the library); kErfcCheb, the FP64 Chebyshev series (few registers; FP32
+// takes the rational fit).
 enum { kErfcFit = 0, kErfcTable = 1, kErfcCheb = 2 };
 
 template <typename R, bool SW>
@@ -145,8 +147,13 @@ struct PairCore {
       const float u = r * P.inv_h;  // exact; 0 <= u <= kDsfN for r <= rc
       const float4 fa = tab[2 * (int)u], fb = tab[2 * (int)u + 1];
       const float t = __builtin_amdgcn_fractf(u);
-      ec = fmaf(fmaf(fmaf(fa.w, t, fa.z), t, fa.y), t, fa.x);
-      gx = fmaf(fmaf(fmaf(fb.w, t, fb.z), t, fb.y), t, fb.x);
+      // r D(r) and r (-r dD/dr), then one factor q q / r for both
+      const float rd = fmaf(fmaf(fmaf(fa.w, t, fa.z), t, fa.y), t, fa.x);
+      const float rf = fmaf(fmaf(fmaf(fb.w, t, fb.z), t, fb.y), t, fb.x);
+      const float qr = qq * rinv;
+      el = qr * rd;
+      fel = qr * rf;
+      return;
     } else if constexpr (sizeof(R) == 8 && E == kErfcCheb) {
       R ex;
       erfc_exp_cheb(P.alpha * r, ec, ex);
