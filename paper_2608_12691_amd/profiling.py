@@ -89,9 +89,10 @@ def traffic(fetch_db, write_db, out_path, command, kernel, copy_bytes):
 
 def counters_summary(db, out_path, command, kernel, launch_us=None):
     """Mean per-launch value of every counter collected for a kernel (sums over the device).
-    With the kernel's launch time (from a trace without counters), the FP32 VALU
-    instruction counts become counter-derived FP32 FLOP/s (64 lanes per wave
-    instruction, FMA = 2 FLOP; an upper bound: inactive lanes are counted)."""
+    With the kernel's launch time (from a trace without counters), the FP32
+    (and FP64) VALU instruction counts become counter-derived FLOP/s (64 lanes
+    per wave instruction, FMA = 2 FLOP; an upper bound: inactive lanes are
+    counted)."""
     con = sqlite3.connect(db)
     rows = con.execute("select counter_name, avg(v), count(*) from (select dispatch_id, counter_name, sum(value) v "
                        "from counters_collection where kernel_name like ? group by dispatch_id, counter_name) "
@@ -99,12 +100,14 @@ def counters_summary(db, out_path, command, kernel, launch_us=None):
     c = {name: v for name, v, _ in rows}
     lines = ["rocprofv3 counters of %s (mean per launch, device totals)" % kernel, "command: %s" % command, ""]
     lines += ["%-28s %16.6g  (%d launches)" % r for r in rows]
-    if launch_us and all(k in c for k in ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_ADD_F32")):
-        flop = 64 * (2 * c["SQ_INSTS_VALU_FMA_F32"] + c["SQ_INSTS_VALU_MUL_F32"] + c["SQ_INSTS_VALU_ADD_F32"] +
-                     c.get("SQ_INSTS_VALU_TRANS_F32", 0.0))
-        lines += ["", "FP32 FLOP per launch (counter-derived, lanes x ops): %.4g" % flop,
-                  "launch time (kernel trace): %.3f us" % launch_us,
-                  "counter-derived FP32 rate: %.3f TFLOP/s" % (flop / (launch_us * 1e-6) / 1e12)]
+    for prec in ("F32", "F64"):
+        keys = ["SQ_INSTS_VALU_%s_%s" % (op, prec) for op in ("FMA", "MUL", "ADD")]
+        if launch_us and all(k in c for k in keys):
+            flop = 64 * (2 * c[keys[0]] + c[keys[1]] + c[keys[2]] + c.get("SQ_INSTS_VALU_TRANS_" + prec, 0.0))
+            name = "FP32" if prec == "F32" else "FP64"
+            lines += ["", "%s FLOP per launch (counter-derived, lanes x ops): %.4g" % (name, flop),
+                      "launch time (kernel trace): %.3f us" % launch_us,
+                      "counter-derived %s rate: %.3f TFLOP/s" % (name, flop / (launch_us * 1e-6) / 1e12)]
     with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
