@@ -224,11 +224,12 @@ KB_KCAL = 0.0019872042586408316  # kcal/(mol K)
 DA_NM2 = 1.0e6 / 4.184           # 1 Da nm^2 in kcal/mol fs^2
 
 
-def _paired_ms(torch, step, W, K):
-    """ms per step of step(t, extra) with and without the extra work, each
-    over K steps after W warm-up steps (HIP events on the current stream)."""
+def _paired_ms(torch, step, W, K, modes=(False, True)):
+    """ms per step of step(t, mode) for each mode (e.g. without and with the
+    extra work), each over K steps after W warm-up steps (HIP events on the
+    current stream)."""
     res = []
-    for extra in (False, True):
+    for extra in modes:
         for t in range(W):
             step(t, extra)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -246,8 +247,9 @@ def dynamics_path(torch, w, traj, lams, W, K):
     """lambda-OPES-d-AFED per step on the timed walk (FP32, LBF schedule):
     the evaluation at the current lambda, 4 dihedral CVs of the solute
     coupled to their s_k (eq. 15), and one theta / s_k step (dual OPES,
-    kernels every 400 steps, TI bins) that writes the next lambda; timed
-    against the same evaluations at a fixed lambda."""
+    kernels every 400 steps, TI bins) that writes the next lambda, with the
+    CVs evaluated in the step's launch; timed against the same evaluations
+    at a fixed lambda, and against the CVs and the step as two launches."""
     import numpy as np
     from paper_2608_12691_amd import alchnb
     s = w.systems[0]
@@ -269,17 +271,19 @@ def dynamics_path(torch, w, traj, lams, W, K):
     out = ctx.new_outputs()
     cv = ctx.dihedrals(traj[0], idx, s=s_view, kappa=kap)
 
-    def step(t, extra):
+    def step(t, mode):
         ctx.compute(traj[t], lam, flags=alchnb.AUTO_REBUILD, out=out)
-        if extra:
+        if mode == "two_launches":
             ctx.dihedrals(traj[t], idx, s=s_view, kappa=kap, forces=out["forces"], out=cv)
             ctx.ld_step(state, out["dudl"], noise, lam, xi=cv["xi"])
+        elif mode == "fused":
+            ctx.ld_step_dafed(state, out["dudl"], noise, lam, traj[t], idx, forces=out["forces"])
 
-    plain, dyn = _paired_ms(torch, step, W, K)
+    plain, two, dyn = _paired_ms(torch, step, W, K, modes=("plain", "two_launches", "fused"))
     flags = ctx.get_flags()
     rec = {"ms_per_step": dyn, "evaluation_ms_per_step": plain, "dynamics_us_per_step": 1e3 * (dyn - plain),
-           "steps": K, "n_cv": n_cv, "deposition_stride": prm["stride"], "lambda_final": float(lam[0]),
-           "device_flags": flags}
+           "two_launch_dynamics_us_per_step": 1e3 * (two - plain), "steps": K, "n_cv": n_cv,
+           "deposition_stride": prm["stride"], "lambda_final": float(lam[0]), "device_flags": flags}
     ctx.close()
     return rec
 

@@ -367,6 +367,21 @@ alch_nb_status alch_nb_ld_step(alch_nb_ctx *ctx, double *d_state, const double *
                                const double *d_noise, int32_t noise_rows, double *d_lambda_out);
 alch_nb_status alch_nb_ld_free_energy(alch_nb_ctx *ctx, const double *d_state, double *d_out);
 
+/* alch_nb_ld_step with the d-AFED coupling (eq. 15) evaluated in the same
+ * launch: the state's n_cv > 0 dihedral CVs of d_idx [n_cv][4] at d_pos
+ * (as alch_nb_dihedrals, with s and kappa read from the state), their
+ * coupling energy into d_u_dafed [1] and force added to d_forces
+ * [N_total][3], the CV values into d_xi [n_cv] (those three may be NULL),
+ * then the step.  With valid indices the results are identical, bit for
+ * bit, to alch_nb_dihedrals(d_s = the state's s, d_kappa = the state's
+ * kappa) followed by alch_nb_ld_step; a CV with an index outside [0, N)
+ * raises ALCH_NB_FLAG_BAD_INDEX, exerts no force and leaves its outputs
+ * unwritten.  ALCH_NB_E_INVALID_ARG for a state without auxiliary
+ * variables.  Device pointers; work on the bound stream. */
+alch_nb_status alch_nb_ld_step_dafed(alch_nb_ctx *ctx, double *d_state, const double *d_dudl, const double *d_pos,
+                                     const int32_t *d_idx, double *d_xi, double *d_u_dafed, double *d_forces,
+                                     const double *d_noise, int32_t noise_rows, double *d_lambda_out);
+
 /* Replica exchange between lambda states (LBF schedule only; the paper's
  * HREX reference protocol, Simulation Details): box r holds state
  * d_state_of[r] of the ascending d_lambda_states [K]; with the LBF potential

@@ -34,7 +34,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "box too small", 3: "unsupported", 
 
 EXPORTED = ["alch_nb_create", "alch_nb_pme_grid", "alch_nb_workspace_size", "alch_nb_bind", "alch_nb_bind_static", "alch_nb_build_list", "alch_nb_compute",
             "alch_nb_backward", "alch_nb_dihedrals", "alch_nb_opes_update", "alch_nb_opes_layout", "alch_nb_opes_init", "alch_nb_opes_state_size",
-            "alch_nb_ld_state_size", "alch_nb_ld_layout", "alch_nb_ld_init", "alch_nb_ld_step",
+            "alch_nb_ld_state_size", "alch_nb_ld_layout", "alch_nb_ld_init", "alch_nb_ld_step", "alch_nb_ld_step_dafed",
             "alch_nb_ld_free_energy", "alch_nb_hrex_init", "alch_nb_hrex_exchange", "alch_nb_capture_begin",
             "alch_nb_capture_end", "alch_nb_export_pairs", "alch_nb_capture_step", "alch_nb_launch_step", "alch_nb_autotune",
             "alch_nb_set_variant", "alch_nb_num_variants", "alch_nb_set_list_mode", "alch_nb_get_list_mode",
@@ -124,6 +124,7 @@ def load():
             "alch_nb_ld_layout": ([P, I32, P, I32], I32),
             "alch_nb_ld_init": ([P, P, P, P, P, P, P], I32),
             "alch_nb_ld_step": ([P, P, P, P, P, I32, P], I32),
+            "alch_nb_ld_step_dafed": ([P, P, P, P, P, P, P, P, P, I32, P], I32),
             "alch_nb_ld_free_energy": ([P, P, P], I32),
             "alch_nb_hrex_init": ([P, P, P], I32),
             "alch_nb_hrex_exchange": ([P, P, P, P, P, P, I32, D, P], I32),
@@ -414,6 +415,16 @@ class Context:
                                       _addr(xi), ctypes.c_void_p(noise.data_ptr()), int(noise.shape[0]),
                                       _addr(lam_out))
         self._check("alch_nb_ld_step", st)
+
+    def ld_step_dafed(self, state, dudl, noise, lam_out, pos, idx, xi=None, u_dafed=None, forces=None):
+        """One lambda-dynamics step that also evaluates the d-AFED dihedral CVs (idx [n_cv, 4] int32) at
+        pos in the same launch, with s and kappa from the state; the coupling force is added to `forces`."""
+        st = self.lib.alch_nb_ld_step_dafed(self.ctx, ctypes.c_void_p(state.data_ptr()),
+                                            ctypes.c_void_p(dudl.data_ptr()), ctypes.c_void_p(pos.data_ptr()),
+                                            ctypes.c_void_p(idx.data_ptr()), _addr(xi), _addr(u_dafed),
+                                            _addr(forces), ctypes.c_void_p(noise.data_ptr()), int(noise.shape[0]),
+                                            _addr(lam_out))
+        self._check("alch_nb_ld_step_dafed", st)
 
     def ld_free_energy(self, state):
         out = self.torch.empty(self.K, dtype=self.torch.float64, device=self.device)

@@ -1071,7 +1071,20 @@ alch_nb_status alch_nb_ld_step(alch_nb_ctx* ctx, double* d_state, const double* 
   if (ctx->ld_ncv < 0) return ALCH_NB_E_NOT_BOUND;  // no state initialised
   if ((ctx->ld_ncv > 0) != (d_xi != nullptr)) return ALCH_NB_E_INVALID_ARG;
   HIPCHK(launch_ld_step(ctx->stream, d_state, ctx->K, ctx->ld_ncv, d_dudl, d_xi, d_noise, noise_rows, d_lambda_out,
-                        ctx->dev.flags));
+                        ctx->dev.flags, LdCv{}));
+  return ALCH_NB_OK;
+}
+
+alch_nb_status alch_nb_ld_step_dafed(alch_nb_ctx* ctx, double* d_state, const double* d_dudl, const double* d_pos,
+                                     const int32_t* d_idx, double* d_xi, double* d_u_dafed, double* d_forces,
+                                     const double* d_noise, int32_t noise_rows, double* d_lambda_out) {
+  if (!ctx || !d_state || !d_dudl || !d_pos || !d_idx || !d_noise || noise_rows < 1) return ALCH_NB_E_INVALID_ARG;
+  if (!is_bound(ctx)) return ALCH_NB_E_NOT_BOUND;
+  if (ctx->ld_ncv < 0) return ALCH_NB_E_NOT_BOUND;  // no state initialised
+  if (ctx->ld_ncv == 0) return ALCH_NB_E_INVALID_ARG;  // no auxiliary variables to couple
+  const LdCv cv{d_pos, d_idx, d_xi, d_u_dafed, d_forces, ctx->dev.reps, ctx->dev.atom_rep, ctx->N};
+  HIPCHK(launch_ld_step(ctx->stream, d_state, ctx->K, ctx->ld_ncv, d_dudl, nullptr, d_noise, noise_rows,
+                        d_lambda_out, ctx->dev.flags, cv));
   return ALCH_NB_OK;
 }
 

@@ -76,8 +76,21 @@ inline double fixed_scale(int precision) { return precision == 0 ? 4294967296.0 
 
 hipError_t launch_ld_init(hipStream_t st, double* state, long long words, const LdInit& in, const double* theta0,
                           const double* s0, const double* mass_s, const double* kappa);
+// The d-AFED CVs evaluated inside the lambda-dynamics step (pos null: the
+// step reads xi from its argument instead).
+struct LdCv {
+  const double* pos;
+  const int* idx;
+  double* xi_out;
+  double* u_dafed;
+  double* forces;
+  const ReplicaInfo* reps;
+  const int* atom_rep;
+  int n_atoms;
+};
 hipError_t launch_ld_step(hipStream_t st, double* state, int K, int n_cv, const double* dudl, const double* xi,
-                          const double* noise, int noise_rows, double* lam_out, unsigned int* flags);
+                          const double* noise, int noise_rows, double* lam_out, unsigned int* flags,
+                          const LdCv& cv);
 hipError_t launch_hrex_init(hipStream_t st, int* state_of, long long* stats, int K);
 hipError_t launch_hrex(hipStream_t st, const double* terms, const double* lam_states, int* state_of, double* lam_out,
                        const double* uniform, int rows, double kT, long long* stats, int K);

@@ -9,9 +9,8 @@
 //   the adds.  k_pgrad_final adds the slots of each atom type in a fixed
 //   order (and clears them for the next pass).
 // - k_backward_finish: -g_k F and g_k dU/dlambda from the last forward.
-// - k_dihedrals: dihedral angles, their Cartesian gradients (from the plane
-//   rotation rates and the invariances, see dihedral_grad), the paper's
-//   eq. 16 sum and the d-AFED coupling (eq. 15).
+// - k_dihedrals: dihedral angles, their Cartesian gradients, the paper's
+//   eq. 16 sum and the d-AFED coupling (eq. 15), one block (dihedral_cv.h).
 // - k_opes: mirror-periodic theta (eq. 3), dual OPES bias (eqs. 11-14),
 //   kernel deposition, generalized force on theta.  FP64, one block;
 //   k_opes_grid refreshes the bias on the output grid after a deposition.
@@ -21,6 +20,7 @@
 
 #include "anb_internal.h"
 #include "anb_kernels.h"
+#include "dihedral_cv.h"
 #include "erfc_coeffs.h"
 #include "lane_ops.h"
 #include "pair_math.h"
@@ -355,116 +355,15 @@ hipError_t launch_backward_finish(const Dev& d, hipStream_t st, int precision, c
 
 // ------------------------------------------------------------ dihedrals
 
-struct V3 {
-  double x, y, z;
-};
-__device__ inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-__device__ inline V3 add(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-__device__ inline V3 scl(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
-__device__ inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
-__device__ inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
-
-// Dihedral of r1..r4 (F = r1 - r2, G = r2 - r3, H = r4 - r3, plane normals
-// A = F x G, B = H x G), xi = atan2((B x A).G/|G|, A.B) in (-pi, pi], and its
-// Cartesian gradient written from the geometry of a torsion: an end atom
-// moves xi only through the rotation of its plane about the axis, at rate
-// |G|/|A|^2 (atom 1, along -A) and |G|/|B|^2 (atom 4, along +B); the two axis
-// atoms then take the shares fixed by translation and rotation invariance,
-// i.e. sum_i dxi/dr_i = 0 and sum_i r_i x dxi/dr_i = 0, which with the axial
-// offsets f = F.G/|G|^2 and h = H.G/|G|^2 of the end atoms gives
-//   dxi/dr2 = -(1 + f) dxi/dr1 - h dxi/dr4,  dxi/dr3 = f dxi/dr1 + (h - 1) dxi/dr4.
-__device__ inline double dihedral_grad(V3 F, V3 G, V3 H, V3 g[4]) {
-  const V3 A = cross(F, G), B = cross(H, G);
-  const double gg = dot(G, G), gn = sqrt(gg);
-  const double y = dot(cross(B, A), G) / gn, x = dot(A, B);
-  const double xi = atan2(y, x);
-  const double aa = dot(A, A), bb = dot(B, B);
-  const V3 g1 = scl(A, -gn / aa);
-  const V3 g4 = scl(B, gn / bb);
-  const double f = dot(F, G) / gg, h = dot(H, G) / gg;
-  g[0] = g1;
-  g[3] = g4;
-  g[1] = sub(scl(g1, -(1.0 + f)), scl(g4, h));
-  g[2] = add(scl(g1, f), scl(g4, h - 1.0));
-  return xi;
-}
-
-__device__ inline double mi1(double v, double L) { return v - L * rint(v / L); }
-
-__global__ void k_dihedrals(const double* __restrict__ pos, int n_cv, const int* __restrict__ idx,
-                            double* __restrict__ xi_out, double* __restrict__ dxi, const double* __restrict__ mass_inv,
-                            double* __restrict__ msum, const double* __restrict__ s, const double* __restrict__ kappa,
-                            double* __restrict__ u_dafed, double* __restrict__ forces, const ReplicaInfo* reps,
-                            const int* atom_rep, int n_atoms, unsigned int* flags) {
-  __shared__ double dval[kBlk];
-  __shared__ double ublk[kBlk];
-  for (int c0 = 0; c0 < n_cv; c0 += kBlk) {
-    const int c = c0 + threadIdx.x;
-    double du = 0.0, d_wrap = 0.0;
-    V3 g[4] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    bool ok = c < n_cv;
-    int a[4] = {0, 0, 0, 0};
-    if (ok) {
-      for (int j = 0; j < 4; ++j) {
-        a[j] = idx[4 * c + j];
-        ok = ok && a[j] >= 0 && a[j] < n_atoms;
-      }
-      if (!ok) atomicOr(flags, 64u);  // invalid atom index: CV skipped
-    }
-    if (ok) {
-      const ReplicaInfo& rp = reps[atom_rep[a[1]]];
-      V3 r[4];
-      for (int j = 0; j < 4; ++j) r[j] = {pos[3 * a[j]], pos[3 * a[j] + 1], pos[3 * a[j] + 2]};
-      V3 F = sub(r[0], r[1]), G = sub(r[1], r[2]), H = sub(r[3], r[2]);
-      F = {mi1(F.x, rp.box[0]), mi1(F.y, rp.box[1]), mi1(F.z, rp.box[2])};
-      G = {mi1(G.x, rp.box[0]), mi1(G.y, rp.box[1]), mi1(G.z, rp.box[2])};
-      H = {mi1(H.x, rp.box[0]), mi1(H.y, rp.box[1]), mi1(H.z, rp.box[2])};
-      const double xi = dihedral_grad(F, G, H, g);
-      xi_out[c] = xi;
-      for (int j = 0; j < 4; ++j) {
-        dxi[12 * c + 3 * j] = g[j].x;
-        dxi[12 * c + 3 * j + 1] = g[j].y;
-        dxi[12 * c + 3 * j + 2] = g[j].z;
-      }
-      if (mass_inv && msum) {
-        double m = 0.0;
-        for (int j = 0; j < 4; ++j) m += mass_inv[a[j]] * dot(g[j], g[j]);
-        msum[c] = m;
-      }
-      if (s && kappa) {
-        // periodic angular displacement wrapped into (-pi, pi]
-        double dd = xi - s[c];
-        dd = dd - 2.0 * M_PI * floor((dd + M_PI) / (2.0 * M_PI));
-        if (dd == -M_PI) dd = M_PI;
-        d_wrap = kappa[c] * dd;
-        du = 0.5 * kappa[c] * dd * dd;
-      }
-    }
-    ublk[threadIdx.x] = du;
-    dval[threadIdx.x] = d_wrap;
-    __syncthreads();
-    if (threadIdx.x == 0 && s && kappa) {
-      // fixed order: energies and forces of this chunk of CVs
-      double acc = u_dafed ? (c0 == 0 ? 0.0 : u_dafed[0]) : 0.0;
-      for (int k = 0; k < kBlk && c0 + k < n_cv; ++k) acc += ublk[k];
-      if (u_dafed) u_dafed[0] = acc;
-    }
-    if (forces && s && kappa) {
-      // serialize the scatter over the CVs of this chunk for a fixed order
-      for (int k = 0; k < kBlk && c0 + k < n_cv; ++k) {
-        if ((int)threadIdx.x == k && ok) {
-          for (int j = 0; j < 4; ++j) {
-            const int aj = idx[4 * c + j];
-            forces[3 * aj] -= d_wrap * g[j].x;
-            forces[3 * aj + 1] -= d_wrap * g[j].y;
-            forces[3 * aj + 2] -= d_wrap * g[j].z;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    __syncthreads();
-  }
+__global__ void __launch_bounds__(kBlk) k_dihedrals(const double* __restrict__ pos, int n_cv,
+                                                    const int* __restrict__ idx, double* __restrict__ xi_out,
+                                                    double* __restrict__ dxi, const double* __restrict__ mass_inv,
+                                                    double* __restrict__ msum, const double* __restrict__ s,
+                                                    const double* __restrict__ kappa, double* __restrict__ u_dafed,
+                                                    double* __restrict__ forces, const ReplicaInfo* reps,
+                                                    const int* atom_rep, int n_atoms, unsigned int* flags) {
+  const dcv::CvOut o{xi_out, dxi, mass_inv, msum, u_dafed, forces};
+  dcv::cv_block<kBlk>(pos, n_cv, idx, s, kappa, o, reps, atom_rep, n_atoms, flags, [](int, bool, double) {});
 }
 
 hipError_t launch_dihedrals(hipStream_t st, const double* pos, int n_cv, const int* idx, double* xi, double* dxi,

@@ -1,8 +1,9 @@
 // Lambda dynamics and d-AFED extended dynamics on the device (FP64).
 //
 // One launch per MD step, after the nonbonded evaluation (and the dihedral
-// CVs when d-AFED is on): block r < K advances replica r's theta, block K
-// the auxiliary variables s_k.  The step reads dU/dlambda of the current
+// CVs when d-AFED is on, or with them: then block K evaluates the CVs and
+// their coupling forces itself): block r < K advances replica r's theta,
+// block K the auxiliary variables s_k.  The step reads dU/dlambda of the current
 // lambda and xi_k of the current positions, and writes the next lambda to
 // the array the next evaluation reads, so a whole step (evaluation,
 // dihedrals, this update) can be captured in one graph.
@@ -27,6 +28,7 @@
 
 #include "anb_internal.h"
 #include "anb_kernels.h"
+#include "dihedral_cv.h"
 
 namespace anb {
 
@@ -192,7 +194,7 @@ __device__ inline bool deposit_one(const Kern& K, double* count, int cap, double
 __global__ void __launch_bounds__(kLdBlk) k_ld_step(double* __restrict__ st, const double* __restrict__ dudl,
                                                     const double* __restrict__ xi, const double* __restrict__ noise,
                                                     int noise_rows, double* __restrict__ lam_out,
-                                                    unsigned int* __restrict__ flags) {
+                                                    unsigned int* __restrict__ flags, LdCv cv) {
   __shared__ double red[kLdBlk / 64];
   __shared__ int redi[kLdBlk / 64];
   const double* G = st;
@@ -280,9 +282,10 @@ __global__ void __launch_bounds__(kLdBlk) k_ld_step(double* __restrict__ st, con
     const double* M = P + n_cv;
     const double* KA = M + n_cv;
     double* F = S + 4 * n_cv;
-    for (int k = threadIdx.x; k < n_cv; k += kLdBlk) {
+    // one BAOAB step of s_k from the CV value xk
+    auto advance = [&](int k, double xk) {
       const double s = S[k];
-      const double f = KA[k] * wrap_pi(xi[k] - s);
+      const double f = KA[k] * wrap_pi(xk - s);
       double p = P[k];
       if (n > 0) p += 0.5 * h * f;
       p += 0.5 * h * f;
@@ -293,6 +296,16 @@ __global__ void __launch_bounds__(kLdBlk) k_ld_step(double* __restrict__ st, con
       S[k] = wrap_pi(q);
       P[k] = p;
       F[k] = f;
+    };
+    if (cv.pos) {
+      // the CVs at the current positions, coupled to the current s_k (their
+      // forces added to cv.forces); each s_k then advances from its own CV
+      // (a CV with an invalid index exerts no force on s_k)
+      const dcv::CvOut o{cv.xi_out, nullptr, nullptr, nullptr, cv.u_dafed, cv.forces};
+      dcv::cv_block<kLdBlk>(cv.pos, n_cv, cv.idx, S, KA, o, cv.reps, cv.atom_rep, cv.n_atoms, flags,
+                            [&](int k, bool ok, double x) { advance(k, ok ? x : S[k]); });
+    } else {
+      for (int k = threadIdx.x; k < n_cv; k += kLdBlk) advance(k, xi[k]);
     }
     __syncthreads();
     if (threadIdx.x == 0) C[LD_C_N] = (double)(n + 1);
@@ -361,9 +374,10 @@ hipError_t launch_ld_init(hipStream_t st, double* state, long long words, const 
 }
 
 hipError_t launch_ld_step(hipStream_t st, double* state, int K, int n_cv, const double* dudl, const double* xi,
-                          const double* noise, int noise_rows, double* lam_out, unsigned int* flags) {
+                          const double* noise, int noise_rows, double* lam_out, unsigned int* flags,
+                          const LdCv& cv) {
   hipLaunchKernelGGL(k_ld_step, dim3(K + (n_cv > 0 ? 1 : 0)), dim3(kLdBlk), 0, st, state, dudl, xi, noise,
-                     noise_rows, lam_out, flags);
+                     noise_rows, lam_out, flags, cv);
   return hipGetLastError();
 }
 

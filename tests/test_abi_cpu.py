@@ -85,6 +85,11 @@ def test_create_plans_workspace(lib):
     # computing before binding is refused without touching the GPU
     assert lib.alch_nb_compute(ctx, ctypes.c_void_p(8), ctypes.c_void_p(8), 1, None) == 6
     assert lib.alch_nb_build_list(ctx, ctypes.c_void_p(8)) == 6
+    # the fused lambda-dynamics step: missing arguments first, then no binding
+    v = ctypes.c_void_p(8)
+    assert lib.alch_nb_ld_step_dafed(ctx, v, v, None, v, None, None, None, v, 1, None) == 1
+    assert lib.alch_nb_ld_step_dafed(ctx, v, v, v, v, None, None, None, v, 0, None) == 1
+    assert lib.alch_nb_ld_step_dafed(ctx, v, v, v, v, None, None, None, v, 1, None) == 6
     # timing: a negative stride is refused; 0 (off) creates no HIP object
     assert lib.alch_nb_set_timing(ctx, -1) == 1
     assert lib.alch_nb_set_timing(ctx, 0) == 0

@@ -150,6 +150,29 @@ def test_dihedrals_and_dafed_against_oracle():
     assert ctx.get_flags() & 64
 
 
+def test_dihedrals_overlapping_many_cvs_against_oracle():
+    """70 CVs over sliding windows of 8 solute atoms (each atom in up to 28
+    entries, 70 > one block's 64-CV chunk): the coupling forces of atoms
+    shared between CVs and chunks against the oracle."""
+    w, _ = _peptide_box()
+    s = w.systems[0]
+    ctx = _ctx(w, 1)
+    pos = ctx.positions(w.systems)
+    sol = np.nonzero(s.is_solute)[0][:8]
+    idx = np.array([[sol[(k + j) % 8] for j in range(4)] for k in range(70)], np.int32)
+    rng = np.random.default_rng(11)
+    sv = torch.tensor(rng.uniform(-np.pi, np.pi, 70), dtype=torch.float64, device=ctx.device)
+    kap = torch.tensor(rng.uniform(50.0, 400.0, 70), dtype=torch.float64, device=ctx.device)
+    forces = torch.zeros_like(pos)
+    r = ctx.dihedrals(pos, torch.tensor(idx, device=ctx.device), s=sv, kappa=kap, forces=forces)
+    torch.cuda.synchronize()
+    ref = OD.cvs(s.positions, idx, s.box, None, sv.cpu().numpy(), kap.cpu().numpy())
+    assert np.allclose(r["xi"].cpu().numpy(), ref["xi"], rtol=0, atol=1e-12)
+    assert float(r["u_dafed"][0]) == pytest.approx(ref["u_dafed"], rel=1e-12)
+    assert _rel(forces.cpu().numpy(), ref["forces"]) < 1e-11
+    assert ctx.get_flags() == 0
+
+
 def test_dihedral_cv_autograd_and_dafed():
     from paper_2608_12691_amd import autograd as AG
     w, idx = _peptide_box()
