@@ -22,7 +22,7 @@ OUT = os.path.join(HERE, "libalchnb.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "alchnb")
 SOURCES = ["alch_nb.cpp", "list_kernels.hip", "tile_kernels.hip", "aux_kernels.hip", "ldyn_kernels.hip",
            "hrex_kernels.hip", "noalloc.hip", "pme_kernels.hip"]
-HEADERS = ["anb_internal.h", "anb_kernels.h", "erfc_coeffs.h", "lane_ops.h", "pair_math.h"]
+HEADERS = ["anb_internal.h", "anb_kernels.h", "dihedral_cv.h", "erfc_coeffs.h", "lane_ops.h", "pair_math.h"]
 ARCH = "gfx950"
 
 
