@@ -59,6 +59,28 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// N sums of one value each per thread, reduced together (each in the order
+// of block_sum, so each result equals block_sum's); red holds
+// kLdBlk / 64 * N doubles.
+template <int N>
+__device__ inline void block_sums(double (&v)[N], double* red) {
+  for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], o);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[(threadIdx.x >> 6) * N + i] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (int w = 0; w < kLdBlk / 64; ++w) s += red[w * N + i];
+    v[i] = s;
+  }
+  __syncthreads();
+}
+
 // Minimum of (key, index) over the block; ties to the lower index.
 __device__ inline void block_argmin(double key, int idx, double* redk, int* redi, double& out_key, int& out_idx) {
   for (int o = 32; o >= 1; o >>= 1) {
@@ -106,20 +128,28 @@ __device__ inline void kernel_value(double theta, double c, double w, double s, 
   }
 }
 
-// rho_hat numerator, derivative and total weight of one variant at theta
-__device__ inline void rho_parts(const Kern& K, int n, double s0, double theta, double* red, double& v, double& dv,
-                                 double& W) {
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int k = threadIdx.x; k < n; k += kLdBlk) {
+// rho_hat numerators, derivatives and total weights of both variants at
+// theta, reduced together: p = {v, dv, W} of the Standard kernels, then of
+// the Explore kernels
+__device__ inline void rho_parts2(const Kern& Ks, int ns, const Kern& Ke, int ne, double s0, double theta,
+                                  double* red6, double (&p)[6]) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) p[i] = 0.0;
+  for (int k = threadIdx.x; k < ns; k += kLdBlk) {
     double g, dg;
-    kernel_value(theta, K.c[k], K.w[k], K.s[k], s0, g, dg);
-    a += g;
-    b += dg;
-    c += K.w[k];
+    kernel_value(theta, Ks.c[k], Ks.w[k], Ks.s[k], s0, g, dg);
+    p[0] += g;
+    p[1] += dg;
+    p[2] += Ks.w[k];
   }
-  v = block_sum(a, red);
-  dv = block_sum(b, red);
-  W = block_sum(c, red);
+  for (int k = threadIdx.x; k < ne; k += kLdBlk) {
+    double g, dg;
+    kernel_value(theta, Ke.c[k], Ke.w[k], Ke.s[k], s0, g, dg);
+    p[3] += g;
+    p[4] += dg;
+    p[5] += Ke.w[k];
+  }
+  block_sums<6>(p, red6);
 }
 
 // mean of rho_hat over the kernel centres
@@ -197,6 +227,7 @@ __global__ void __launch_bounds__(kLdBlk) k_ld_step(double* __restrict__ st, con
                                                     unsigned int* __restrict__ flags, LdCv cv) {
   __shared__ double red[kLdBlk / 64];
   __shared__ int redi[kLdBlk / 64];
+  __shared__ double red6[kLdBlk / 64 * 6];
   const double* G = st;
   const int K = (int)G[LD_K], n_cv = (int)G[LD_NCV], cap = (int)G[LD_CAP], bins = (int)G[LD_BINS];
   const int stride = (int)G[LD_STRIDE];
@@ -216,15 +247,14 @@ __global__ void __launch_bounds__(kLdBlk) k_ld_step(double* __restrict__ st, con
     auto bias = [&](double x, double& u, double& du) {
       u = du = 0.0;
       if (R[LD_R_NSTD] <= 0.0) return;
-      double v, dv, W;
-      rho_parts(Ks, (int)R[LD_R_NSTD], s0, x, red, v, dv, W);
-      const double as = v / W / R[LD_R_RBAR_STD] + eps_s;
+      double q[6];
+      rho_parts2(Ks, (int)R[LD_R_NSTD], Ke, (int)R[LD_R_NEXPL], s0, x, red6, q);
+      const double as = q[0] / q[2] / R[LD_R_RBAR_STD] + eps_s;
       u += nu_s * kT * log(as);
-      du += nu_s * kT * (dv / W / R[LD_R_RBAR_STD]) / as;
-      rho_parts(Ke, (int)R[LD_R_NEXPL], s0, x, red, v, dv, W);
-      const double ae = v / W / R[LD_R_RBAR_EXPL] + eps_e;
+      du += nu_s * kT * (q[1] / q[2] / R[LD_R_RBAR_STD]) / as;
+      const double ae = q[3] / q[5] / R[LD_R_RBAR_EXPL] + eps_e;
       u += nu_e * kT * log(ae);
-      du += nu_e * kT * (dv / W / R[LD_R_RBAR_EXPL]) / ae;
+      du += nu_e * kT * (q[4] / q[5] / R[LD_R_RBAR_EXPL]) / ae;
     };
     if (stride > 0 && n % stride == 0) {
       double u0, du0;

@@ -222,6 +222,62 @@ def test_ld_step_dafed_matches_the_two_call_step_bitwise(n_cv):
     assert moved <= set(idx[1:].ravel().tolist())
 
 
+def test_ld_step_dafed_in_one_graph_matches_eager():
+    """A whole lambda-OPES-d-AFED step (evaluation at the current lambda,
+    CVs with their coupling forces and the theta / s_k update) captured once
+    and replayed on a 633-atom walk, the positions copied into the captured
+    buffer before each replay: every replay's lambda, and the final forces,
+    CVs' coupling energy and state, equal the eager steps bit for bit."""
+    from paper_2608_12691_amd import alchnb
+    w = workload(1)
+    s = w.systems[0]
+    steps, n_cv = 30, 3
+    p = _params(n_cv, 5, 1.0, cap=16, bins=5)
+    sol = np.nonzero(s.is_solute)[0][:8]
+    idx = np.array([sol[k:k + 4] for k in range(n_cv)], dtype=np.int32)
+    walk = S.perturbation_walk(s, steps, 0.01, seed=1234)
+    rng = np.random.Generator(np.random.PCG64(808))
+    noise = rng.standard_normal((steps, 1 + n_cv))
+    mass_s = np.full(n_cv, 50.0 * L.DA_NM2_TO_KCAL_FS2 * 1e-3)
+    kappa = np.full(n_cv, 239.0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    runs = {}
+    for mode in ("eager", "graph"):
+        with torch.cuda.stream(stream):
+            ctx = alchnb.from_workload(w, precision=alchnb.FP32_FIXED, schedule=alchnb.LBF_DSF)
+            state, lay = ctx.ld_init(p, [0.35], s0=np.zeros(n_cv), mass_s=mass_s, kappa=kappa)
+            nz = torch.as_tensor(noise, device=dev)
+            di = torch.as_tensor(idx, device=dev)
+            lam = ctx.lambdas([0.35])
+            x = ctx.positions(walk[0])
+            out = ctx.new_outputs()
+            u = torch.zeros(1, dtype=torch.float64, device=dev)
+            ctx.compute_checked(x, lam, flags=alchnb.FORCE_REBUILD, out=out)
+            if mode == "graph":
+                ctx.capture_begin()
+                ctx.compute(x, lam, flags=alchnb.AUTO_REBUILD, out=out)
+                ctx.ld_step_dafed(state, out["dudl"], nz, lam, x, di, u_dafed=u, forces=out["forces"])
+                ctx.capture_end()
+        hist = []
+        for t in range(steps):
+            with torch.cuda.stream(stream):
+                x.copy_(torch.as_tensor(walk[t], device=dev))
+                if mode == "graph":
+                    ctx.launch_step()
+                else:
+                    ctx.compute(x, lam, flags=alchnb.AUTO_REBUILD, out=out)
+                    ctx.ld_step_dafed(state, out["dudl"], nz, lam, x, di, u_dafed=u, forces=out["forces"])
+            stream.synchronize()
+            hist.append(float(lam[0]))
+        print("%s: lambda %.6f" % (mode, hist[-1]), flush=True)
+        assert ctx.get_flags() == 0
+        runs[mode] = (hist, out["forces"].cpu(), u.cpu(), state.cpu())
+    (ha, fa, ua, sa), (hb, fb, ub, sb) = runs["eager"], runs["graph"]
+    assert ha == hb
+    assert torch.equal(fa, fb) and torch.equal(ua, ub) and torch.equal(sa, sb)
+
+
 def test_ld_capacity_flag_drops_kernels_without_fault():
     """A store of two kernels per variant with no merging: later depositions
     are dropped and raise the capacity flag; the dynamics continue."""
