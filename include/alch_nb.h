@@ -81,8 +81,8 @@ enum {
   ALCH_NB_FLAG_LAMBDA_RANGE = 8u,   /* a lambda outside [0,1] was clamped */
   ALCH_NB_FLAG_CAPACITY = 16u,      /* the list did not fit its capacity; results of that call are invalid */
   ALCH_NB_FLAG_BARRIER_TIMEOUT = 32u,/* a list-build phase waited too long for the others; results invalid */
-  ALCH_NB_FLAG_BAD_INDEX = 64u,      /* alch_nb_dihedrals met an atom index outside [0, N); that CV was skipped */
-  ALCH_NB_FLAG_LD_CAPACITY = 128u    /* alch_nb_ld_step could not store an OPES kernel (capacity); it was dropped */
+  ALCH_NB_FLAG_BAD_INDEX = 64u,      /* alch_nb_dihedrals or alch_nb_ld_step_dafed met an atom index outside [0, N); that CV was skipped */
+  ALCH_NB_FLAG_LD_CAPACITY = 128u    /* alch_nb_ld_step(_dafed) could not store an OPES kernel (capacity); it was dropped */
 };
 
 /* energy-term slots of alch_nb_out.terms, per system */
@@ -368,7 +368,8 @@ alch_nb_status alch_nb_ld_step(alch_nb_ctx *ctx, double *d_state, const double *
 alch_nb_status alch_nb_ld_free_energy(alch_nb_ctx *ctx, const double *d_state, double *d_out);
 
 /* alch_nb_ld_step with the d-AFED coupling (eq. 15) evaluated in the same
- * launch: the state's n_cv > 0 dihedral CVs of d_idx [n_cv][4] at d_pos
+ * launch: the state's n_cv > 0 dihedral CVs of d_idx [n_cv][4] (n_cv of
+ * the state, global atom indices) at d_pos
  * (as alch_nb_dihedrals, with s and kappa read from the state), their
  * coupling energy into d_u_dafed [1] and force added to d_forces
  * [N_total][3], the CV values into d_xi [n_cv] (those three may be NULL),
@@ -405,8 +406,9 @@ alch_nb_status alch_nb_hrex_exchange(alch_nb_ctx *ctx, const double *d_terms, co
 
 /* Record every call made between alch_nb_capture_begin() and
  * alch_nb_capture_end() on the bound stream (e.g. alch_nb_compute,
- * alch_nb_dihedrals, alch_nb_ld_step, alch_nb_hrex_exchange) as one HIP
- * graph, replayed with alch_nb_launch_step(); the pointers are captured.
+ * alch_nb_dihedrals, alch_nb_ld_step, alch_nb_ld_step_dafed,
+ * alch_nb_hrex_exchange) as one HIP graph, replayed with
+ * alch_nb_launch_step(); the pointers are captured.
  * Calls that synchronize (flags, statistics, pair export) are not allowed
  * in between. */
 alch_nb_status alch_nb_capture_begin(alch_nb_ctx *ctx);
