@@ -628,7 +628,8 @@ def main():
         v64 = r64["n_pairs"] / r64["elapsed"]
         F32, F64 = r32["forces"], r64["forces"]
         line["fp64"] = {"value": v64, "ms_per_step": 1e3 * r64["elapsed"] / K,
-                        "tile_us": r64["tile_ms"] * 1e3 if r64["tile_ms"] else None}
+                        "tile_us": r64["tile_ms"] * 1e3 if r64["tile_ms"] else None,
+                        "variant": r64["stats"]["variant"]}
         line["fp32_over_fp64"] = value / v64
         line["fp32_error_vs_fp64"] = {
             "force_rms_rel": float(np.sqrt(((F32 - F64) ** 2).sum() / (F64 ** 2).sum())),
