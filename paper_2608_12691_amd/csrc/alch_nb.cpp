@@ -106,6 +106,7 @@ struct alch_nb_ctx {
   int pme_tab = 0;  // entries of the axis tables
   double pme_qscale = 0;  // fixed-point units per e of the charge grids
   int pme_tiles[3] = {0, 0, 0};
+  int pme_planes = 0;  // y and z transforms per plane: the largest x edge (0: by line tiles)
   std::vector<PmePair> pme_pairs;
 };
 
@@ -592,6 +593,18 @@ alch_nb_status alch_nb_create(const alch_nb_params* prm, const alch_nb_system* s
     ctx->pme_points = pts;
     ctx->pme_tab = tab;
     for (int a = 0; a < 3; ++a) ctx->pme_tiles[a] = tiles[a];
+    // one block per y-z plane when every box's plane fits in LDS
+    // (ALCHNB_PME_FFT=lines keeps the line tiles)
+    {
+      int n0max = 0;
+      bool fit = true;
+      for (const PmeBox& B : ctx->pme_box) {
+        n0max = std::max(n0max, B.n[0]);
+        fit = fit && (long long)B.n[1] * B.n[2] <= kPmePlanePts;
+      }
+      const char* env = std::getenv("ALCHNB_PME_FFT");
+      ctx->pme_planes = fit && !(env && std::strcmp(env, "lines") == 0) ? n0max : 0;
+    }
     // charge-grid scale: a power of two that keeps the largest possible grid
     // value (the box's sum of |q_i|) below 2^62 units, at most 2^52
     double qmax = 1.0;
@@ -797,7 +810,7 @@ static alch_nb_status enqueue_compute(alch_nb_ctx* ctx, const double* pos, const
     HIPCHK(hipEventRecord(ctx->ev[2 * ctx->n_timed + 1], st));
     ctx->n_timed++;
   }
-  if (ctx->pme) HIPCHK(launch_pme(d, st, pos, p.schedule, p.precision));
+  if (ctx->pme) HIPCHK(launch_pme(d, st, pos, p.schedule, p.precision, ctx->pme_planes));
   HIPCHK(launch_finalize(d, st, p.precision, p.schedule, out ? out->terms : nullptr, out ? out->forces : nullptr,
                          out ? out->dudl : nullptr, out ? reinterpret_cast<long long*>(out->n_pairs) : nullptr));
   return ALCH_NB_OK;

@@ -55,7 +55,11 @@ hipError_t launch_finalize(const Dev& d, hipStream_t st, int precision, int sche
                            double* forces, double* dudl, long long* n_pairs);
 // Smooth-PME reciprocal space, self and excluded-pair parts of every box
 // (after the tile kernel, before the final reduction that adds them).
-hipError_t launch_pme(const Dev& d, hipStream_t st, const double* pos, int schedule, int precision);
+// yz_planes > 0: the y and z transforms of each grid plane in one block
+// (every box's y-z plane holds at most kPmePlanePts points; yz_planes is
+// the largest x edge); 0: the y and z passes by line tiles.
+constexpr int kPmePlanePts = 4096;
+hipError_t launch_pme(const Dev& d, hipStream_t st, const double* pos, int schedule, int precision, int yz_planes);
 // The influence-function table and the per-box constants (at bind).
 hipError_t launch_pme_init(const Dev& d, hipStream_t st);
 // pair inputs from the last forward's slot coordinates and list

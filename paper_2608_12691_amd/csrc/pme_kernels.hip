@@ -18,16 +18,18 @@
 //   k_pme_fft x2    forward transforms of Z = Q_S + i Q_W along z, then y: a
 //                   block per tile of up to 16 adjacent lines in LDS (the z
 //                   pass reads and clears the integer grids); mixed-radix
-//                   Stockham passes (radices 5, 4, 3, 2);
+//                   Stockham passes (radices 5, 4, 3, 2); for grids whose
+//                   y-z planes fit in LDS, k_pme_fft_yz does both passes,
+//                   one block per plane;
 //   k_pme_xconv     per tile of x-lines with their mirror lines: forward
 //                   transforms along x, the convolution (spectra of Q_S and
 //                   Q_W through Z(-m) = conj, the influence function C(m),
 //                   the S-S, W-W and S-W energies, G_S + i G_W with
 //                   G_S = C (S + c W), G_W = C (W + c S)), inverse transforms
 //                   along x;
-//   k_pme_fft x2    inverse transforms along y, then z: the grid then holds
-//                   the potentials dU/dQ_S (real part) and dU/dQ_W
-//                   (imaginary part);
+//   k_pme_fft x2    inverse transforms along y, then z (or k_pme_fft_yz):
+//                   the grid then holds the potentials dU/dQ_S (real part)
+//                   and dU/dQ_W (imaginary part);
 //   k_pme_gather    kScSplit blocks per super-cluster: the sub-grid of the
 //                   potential staged in LDS, four threads per atom summing
 //                   -q grad(sum_k M M M G) into the fixed-point force sums.
@@ -50,9 +52,14 @@ constexpr int kPmeBlk = 256;
 constexpr int kScSplit = 2;
 static_assert(kSc % kScSplit == 0, "equal slot ranges");
 constexpr int kTilePts = 1024;  // points of an FFT tile (T(n) lines of n points)
+constexpr int kPlaneBlk = 1024; // threads of a y-z plane transform (one block per compute unit by its LDS)
 static_assert(kPmeMaxN <= kTilePts, "a tile holds at least one line");
 
+// (no multiply-add contraction in the transforms: every kernel that runs a
+// Stockham pass then rounds each product and sum the same way, whatever
+// the code around it)
 __device__ inline double2 cmul(double2 a, double2 b) {
+#pragma clang fp contract(off)
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
@@ -373,13 +380,33 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_spread(Dev d, const double* __r
 
 // One Stockham pass of radix R over `lines` lines of n points in LDS
 // (point i of line l at l * lstride + i * estride), the butterflies of all
-// lines spread over the block.
+// lines spread over the block.  The R-point DFTs are written out with the
+// R-th roots of unity as constants, w = exp(-2 pi i / R) forward and its
+// conjugate inverse (sg = -1 / +1 is the sign of the imaginary part):
+//   R = 2: y0 = a0 + a1, y1 = a0 - a1;
+//   R = 4 (w = sg i): t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3,
+//     t3 = sg i (a1 - a3); y0 = t0 + t2, y2 = t0 - t2, y1 = t1 + t3,
+//     y3 = t1 - t3;
+//   R = 3 (w = -1/2 + sg i sin(2 pi/3)): t = a0 - (a1 + a2)/2,
+//     u = sg i sin(2 pi/3) (a1 - a2); y0 = a0 + a1 + a2, y1 = t + u, y2 = t - u;
+//   R = 5 (w^k = cos(2 pi k/5) + sg i sin(2 pi k/5)): with b1 = a1 + a4,
+//     b2 = a2 + a3, d1 = a1 - a4, d2 = a2 - a3, c_k and s_k the cosine and
+//     sine of 2 pi k/5: y0 = a0 + b1 + b2; y1, y4 = t1 +- u1 with
+//     t1 = a0 + c1 b1 + c2 b2, u1 = sg i (s1 d1 + s2 d2); y2, y3 = t2 +- u2
+//     with t2 = a0 + c2 b1 + c1 b2, u2 = sg i (s2 d1 - s1 d2).
 template <int R>
 __device__ inline void fft_stage(const double2* __restrict__ src, double2* __restrict__ dst, int n, int Ns,
                                  int lines, int lstride, int estride, const double2* __restrict__ W, bool inv) {
+#pragma clang fp contract(off)
   const int m = n / R;
   const int step = n / (Ns * R);
   const int total = lines * m;
+  const double sg = inv ? 1.0 : -1.0;
+  // sg i z
+  auto rot = [&](double2 z) { return make_double2(-sg * z.y, sg * z.x); };
+  auto add = [](double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); };
+  auto sub = [](double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); };
+  auto scl = [](double2 a, double c) { return make_double2(a.x * c, a.y * c); };
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     const int line = idx / m, j = idx - line * m;
     const int k = j % Ns;
@@ -393,22 +420,44 @@ __device__ inline void fft_stage(const double2* __restrict__ src, double2* __res
       if (inv) t.y = -t.y;
       v[r] = cmul(v[r], t);
     }
-    // the R-point DFT, each output straight to LDS (no second register array)
+    double2 y[R];
+    if constexpr (R == 2) {
+      y[0] = add(v[0], v[1]);
+      y[1] = sub(v[0], v[1]);
+    } else if constexpr (R == 4) {
+      const double2 t0 = add(v[0], v[2]), t1 = sub(v[0], v[2]), t2 = add(v[1], v[3]), t3 = rot(sub(v[1], v[3]));
+      y[0] = add(t0, t2);
+      y[2] = sub(t0, t2);
+      y[1] = add(t1, t3);
+      y[3] = sub(t1, t3);
+    } else if constexpr (R == 3) {
+      constexpr double s3 = 0.8660254037844387;  // sin(2 pi/3)
+      const double2 b = add(v[1], v[2]);
+      const double2 t = sub(v[0], scl(b, 0.5));
+      const double2 u = rot(scl(sub(v[1], v[2]), s3));
+      y[0] = add(v[0], b);
+      y[1] = add(t, u);
+      y[2] = sub(t, u);
+    } else {
+      static_assert(R == 5, "radices 2, 3, 4 and 5");
+      constexpr double c1 = 0.30901699437494745, c2 = -0.8090169943749473;  // cos(2 pi/5), cos(4 pi/5)
+      constexpr double s1 = 0.9510565162951535, s2 = 0.5877852522924732;    // sin(2 pi/5), sin(4 pi/5)
+      const double2 b1 = add(v[1], v[4]), b2 = add(v[2], v[3]);
+      const double2 d1 = sub(v[1], v[4]), d2 = sub(v[2], v[3]);
+      y[0] = add(add(v[0], b1), b2);
+      const double2 t1 = add(add(v[0], scl(b1, c1)), scl(b2, c2));
+      const double2 u1 = rot(add(scl(d1, s1), scl(d2, s2)));
+      const double2 t2 = add(add(v[0], scl(b1, c2)), scl(b2, c1));
+      const double2 u2 = rot(sub(scl(d1, s2), scl(d2, s1)));
+      y[1] = add(t1, u1);
+      y[4] = sub(t1, u1);
+      y[2] = add(t2, u2);
+      y[3] = sub(t2, u2);
+    }
     double2* o_line = dst + line * lstride;
     const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      double2 acc = v[0];
-#pragma unroll
-      for (int r = 1; r < R; ++r) {
-        double2 t = W[((q * r) % R) * m];
-        if (inv) t.y = -t.y;
-        const double2 p = cmul(v[r], t);
-        acc.x += p.x;
-        acc.y += p.y;
-      }
-      o_line[(base + q * Ns) * estride] = acc;
-    }
+    for (int q = 0; q < R; ++q) o_line[(base + q * Ns) * estride] = y[q];
   }
 }
 
@@ -507,6 +556,52 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_fft(Dev d, int axis, int inv, i
     const int li = axis == 2 ? e / n : e % nl, j = axis == 2 ? e - li * n : e / nl;
     g[line_addr(axis, B, l0 + li, j)] = res[li * n + j];
   }
+}
+
+// The y and z passes of one y-z plane per block, for grids whose planes fit
+// in LDS: block (k, ix) (k = blockIdx / max_n0; blocks past box k's x edge
+// return) stages plane ix of box k, transforms its z rows and its y columns
+// with the passes of the line tiles (forward: z then y, from the integer
+// grids, which are cleared; inverse: y then z), and writes it back.  Every
+// line receives the same operations as in the line tiles, so the results
+// are the same; the two passes take one launch.
+__global__ void __launch_bounds__(kPlaneBlk) k_pme_fft_yz(Dev d, int max_n0, int inv) {
+  __shared__ double2 b0[kPmePlanePts], b1[kPmePlanePts], W1[kPmeMaxN], W2[kPmeMaxN];
+  const int k = (int)blockIdx.x / max_n0, ix = (int)blockIdx.x - k * max_n0;
+  const PmeBox B = d.pme_box[k];
+  if (ix >= B.n[0]) return;
+  const int n1 = B.n[1], n2 = B.n[2], np = n1 * n2;
+  for (int e = threadIdx.x; e < n1; e += blockDim.x) W1[e] = d.pme_roots[B.tab[1] + e];
+  for (int e = threadIdx.x; e < n2; e += blockDim.x) W2[e] = d.pme_roots[B.tab[2] + e];
+  // plane ix: point (iy, iz) at ix n1 n2 + iy n2 + iz
+  const long long base = B.off + (long long)ix * np;
+  double2* g = d.pme_grid + base;
+  for (int e = threadIdx.x; e < np; e += blockDim.x) {
+    double2 v;
+    if (!inv) {
+      unsigned long long* qs = d.pme_q + base + e;
+      unsigned long long* qw = qs + d.pme_points;
+      const long long x = (long long)*qs, y = (long long)*qw;
+      *qs = 0ull;
+      *qw = 0ull;
+      const double inv_q = 1.0 / d.pme_qscale;
+      v = make_double2((double)x * inv_q, (double)y * inv_q);
+    } else {
+      v = g[e];
+    }
+    b0[e] = v;
+  }
+  __syncthreads();
+  int src = 0;
+  if (!inv) {
+    fft_lines(b0, b1, src, n2, n1, n2, 1, W2, false);  // z rows
+    fft_lines(b0, b1, src, n1, n2, 1, n2, W1, false);  // y columns
+  } else {
+    fft_lines(b0, b1, src, n1, n2, 1, n2, W1, true);
+    fft_lines(b0, b1, src, n2, n1, n2, 1, W2, true);
+  }
+  const double2* res = src ? b1 : b0;
+  for (int e = threadIdx.x; e < np; e += blockDim.x) g[e] = res[e];
 }
 
 // At bind: the influence function C(m) = k_e/(pi V) exp(-pi^2 |m|^2/a^2)/|m|^2
@@ -763,28 +858,38 @@ __global__ void __launch_bounds__(kPmeBlk) k_pme_gather(Dev d, const double* __r
 }
 
 template <int N>
-hipError_t launch_pme_order(const Dev& d, hipStream_t st, const double* pos, int schedule, double fscale) {
+hipError_t launch_pme_order(const Dev& d, hipStream_t st, const double* pos, int schedule, double fscale,
+                            int yz_planes) {
   const dim3 parts(kPmeParts, d.n_reps);
   hipLaunchKernelGGL(k_pme_spread<N>, dim3(kScSplit * d.sc_cap + kPmeParts * d.n_reps), dim3(kPmeBlk), 0, st, d,
                      pos, schedule,
                      fscale);
-  hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[2]), dim3(kPmeBlk), 0, st, d, 2, 0, 1);
-  hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[1]), dim3(kPmeBlk), 0, st, d, 1, 0, 0);
+  const dim3 planes(yz_planes * d.n_reps);
+  if (yz_planes > 0) {
+    hipLaunchKernelGGL(k_pme_fft_yz, planes, dim3(kPlaneBlk), 0, st, d, yz_planes, 0);
+  } else {
+    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[2]), dim3(kPmeBlk), 0, st, d, 2, 0, 1);
+    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[1]), dim3(kPmeBlk), 0, st, d, 1, 0, 0);
+  }
   hipLaunchKernelGGL(k_pme_xconv, parts, dim3(kPmeBlk), 0, st, d, schedule);
-  hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[1]), dim3(kPmeBlk), 0, st, d, 1, 1, 0);
-  hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[2]), dim3(kPmeBlk), 0, st, d, 2, 1, 0);
+  if (yz_planes > 0) {
+    hipLaunchKernelGGL(k_pme_fft_yz, planes, dim3(kPlaneBlk), 0, st, d, yz_planes, 1);
+  } else {
+    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[1]), dim3(kPmeBlk), 0, st, d, 1, 1, 0);
+    hipLaunchKernelGGL(k_pme_fft, dim3(d.pme_tiles[2]), dim3(kPmeBlk), 0, st, d, 2, 1, 0);
+  }
   hipLaunchKernelGGL(k_pme_gather<N>, dim3(kScSplit * d.sc_cap), dim3(kPmeBlk), 0, st, d, pos, fscale);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_pme(const Dev& d, hipStream_t st, const double* pos, int schedule, int precision) {
+hipError_t launch_pme(const Dev& d, hipStream_t st, const double* pos, int schedule, int precision, int yz_planes) {
   const double fs = fixed_scale(precision);
   switch (d.pme_order) {
-    case 4: return launch_pme_order<4>(d, st, pos, schedule, fs);
-    case 5: return launch_pme_order<5>(d, st, pos, schedule, fs);
-    case 6: return launch_pme_order<6>(d, st, pos, schedule, fs);
+    case 4: return launch_pme_order<4>(d, st, pos, schedule, fs, yz_planes);
+    case 5: return launch_pme_order<5>(d, st, pos, schedule, fs, yz_planes);
+    case 6: return launch_pme_order<6>(d, st, pos, schedule, fs, yz_planes);
     default: return hipErrorInvalidValue;
   }
 }

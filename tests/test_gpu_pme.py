@@ -197,6 +197,36 @@ def test_pme_repeats_are_bit_identical_and_graph_replay_matches_eager():
             assert np.array_equal(a[k], b[k]), (t, k)
 
 
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp32", "fp64"])
+def test_pme_plane_transforms_match_line_tiles_bitwise(precision, monkeypatch):
+    """The y and z transforms one y-z plane per block (the default where the
+    planes fit in LDS) against the line tiles (ALCHNB_PME_FFT=lines): the
+    8,973-atom box (45^3) and a ragged batch of two grids with an empty box
+    give identical forces, terms and dU/dlambda."""
+    rng = np.random.Generator(np.random.PCG64(4))
+    w1 = workload(1)
+    boxes = [S.random_tiny_system(rng, 300, 22.0, n_solute=6, n_types=w1.ff.n_types, min_dist=2.0),
+             S.System(positions=np.zeros((0, 3)), types=np.zeros(0, np.int32), is_solute=np.zeros(0, np.uint8),
+                      exclusions=np.zeros((0, 2), np.int32), box=np.full(3, 25.0), molecule=np.zeros(0, np.int32)),
+             S.random_tiny_system(rng, 700, 27.0, n_solute=6, n_types=w1.ff.n_types, min_dist=2.0)]
+    ragged = S.Workload(name="ragged", systems=boxes, ff=w1.ff, cutoff=9.0, skin=1.0, switch_width=1.0,
+                        dsf_alpha=ALPHA, sc_alpha=0.5, lambdas=np.array([0.3, 0.5, 0.7]), seed=4)
+    for w, schedule in ((workload(2), O.LBF), (ragged, O.BEUTLER)):
+        res = []
+        for mode in ("planes", "lines"):
+            if mode == "lines":
+                monkeypatch.setenv("ALCHNB_PME_FFT", "lines")
+            else:
+                monkeypatch.delenv("ALCHNB_PME_FFT", raising=False)
+            ctx = _ctx(w, precision, schedule)
+            r = to_numpy(ctx.compute_checked(ctx.positions(w.systems), ctx.lambdas(w.lambdas), flags=2))
+            assert r["flags"] == 0
+            res.append(r)
+            print("%s %s: dU/dlambda %s" % (w.name, mode, r["dudl"]), flush=True)
+        for k in ("forces", "terms", "dudl", "n_pairs"):
+            assert np.array_equal(res[0][k], res[1][k]), (w.name, k)
+
+
 def test_pme_backward_position_and_lambda_gradients():
     """dL/dx = sum_k g_k dU_k/dx = -g forces and dL/dlambda = g dU/dlambda
     come from the forward's state; the per-type gradients are refused."""
