@@ -222,6 +222,59 @@ def test_ld_step_dafed_matches_the_two_call_step_bitwise(n_cv):
     assert moved <= set(idx[1:].ravel().tolist())
 
 
+def test_ld_step_dafed_three_boxes_matches_the_two_call_step_bitwise():
+    """Three boxes (one empty) with their own theta, and CVs in the first and
+    the third box (global indices, each CV in its own box's minimum image):
+    the fused step against alch_nb_dihedrals + alch_nb_ld_step, bit for bit
+    over 25 steps of a small random walk."""
+    from paper_2608_12691_amd import alchnb
+    rng = np.random.Generator(np.random.PCG64(606))
+    w1 = workload(1)
+    boxes = [S.random_tiny_system(rng, 200, 20.0, n_solute=8, n_types=w1.ff.n_types, min_dist=2.0),
+             S.System(positions=np.zeros((0, 3)), types=np.zeros(0, np.int32), is_solute=np.zeros(0, np.uint8),
+                      exclusions=np.zeros((0, 2), np.int32), box=np.full(3, 20.0), molecule=np.zeros(0, np.int32)),
+             S.random_tiny_system(rng, 300, 22.0, n_solute=8, n_types=w1.ff.n_types, min_dist=2.0)]
+    w = S.Workload(name="three", systems=boxes, ff=w1.ff, cutoff=9.0, skin=1.0, switch_width=1.0, dsf_alpha=0.2,
+                   sc_alpha=0.5, lambdas=np.array([0.2, 0.5, 0.8]), seed=606)
+    off = np.concatenate([[0], np.cumsum([b.n_atoms for b in boxes])])
+    s0 = np.nonzero(boxes[0].is_solute)[0] + off[0]
+    s2 = np.nonzero(boxes[2].is_solute)[0] + off[2]
+    idx = np.array([s0[0:4], s0[2:6], s2[0:4], s2[3:7], s2[[1, 3, 5, 7]]], dtype=np.int32)
+    n_cv, steps = len(idx), 25
+    ctx = alchnb.from_workload(w, precision=alchnb.FP64, schedule=alchnb.LBF_DSF)
+    p = _params(n_cv, 6, 1.0, cap=16, bins=5)
+    kappa = rng.uniform(100.0, 300.0, n_cv)
+    mass_s = np.full(n_cv, 50.0 * L.DA_NM2_TO_KCAL_FS2 * 1e-3)
+    th0 = [0.2, 0.5, 0.8]
+    dev = torch.device("cuda:0")
+    nz = torch.as_tensor(rng.standard_normal((steps, 3 + n_cv)), device=dev)
+    sa, lay = ctx.ld_init(p, th0, s0=np.zeros(n_cv), mass_s=mass_s, kappa=kappa)
+    torch.cuda.synchronize()  # the binding keeps one init's inputs alive
+    sb, _ = ctx.ld_init(p, th0, s0=np.zeros(n_cv), mass_s=mass_s, kappa=kappa)
+    s_view = sa[lay["cv_s"]:lay["cv_s"] + n_cv]
+    kap = torch.as_tensor(kappa, dtype=torch.float64, device=dev)
+    di = torch.as_tensor(idx, device=dev)
+    la, lb = ctx.lambdas(th0), ctx.lambdas(th0)
+    out = ctx.new_outputs()
+    xb = torch.zeros(n_cv, dtype=torch.float64, device=dev)
+    ub = torch.zeros(1, dtype=torch.float64, device=dev)
+    x0 = np.concatenate([b.positions for b in boxes])
+    walk = x0[None] + np.cumsum(np.concatenate([np.zeros((1,) + x0.shape), rng.normal(0.0, 0.01, (steps - 1,) + x0.shape)]), axis=0)
+    cv = None
+    for t in range(steps):
+        x = ctx.positions(walk[t])
+        ctx.compute(x, la, flags=alchnb.AUTO_REBUILD, out=out)
+        fa, fb = out["forces"].clone(), out["forces"].clone()
+        cv = ctx.dihedrals(x, di, s=s_view, kappa=kap, forces=fa, out=cv)
+        ctx.ld_step(sa, out["dudl"], nz, la, xi=cv["xi"])
+        ctx.ld_step_dafed(sb, out["dudl"], nz, lb, x, di, xi=xb, u_dafed=ub, forces=fb)
+        torch.cuda.synchronize()
+        assert torch.equal(fa, fb) and torch.equal(cv["xi"], xb) and torch.equal(cv["u_dafed"], ub), t
+        assert torch.equal(la, lb) and torch.equal(sa, sb), t
+    assert ctx.get_flags() == 0
+    assert float(ub[0]) > 0.0
+
+
 def test_ld_step_dafed_in_one_graph_matches_eager():
     """A whole lambda-OPES-d-AFED step (evaluation at the current lambda,
     CVs with their coupling forces and the theta / s_k update) captured once
