@@ -494,29 +494,30 @@ __global__ void __launch_bounds__(kBlk, sizeof(R) == 4 ? 4 : 1) k_tile(Dev d, Po
   __shared__ R fia_all[kBlk / 64][3][kSc];
   R* fia = &fia_all[threadIdx.x >> 6][0][0];
   const int il = lane & 7, jl = lane >> 3;
-  // FP32 DSF pieces, once per block
-  __shared__ float4 dsf[sizeof(R) == 4 ? kDsfEntries : 1];
-  if (sizeof(R) == 4) {
-    for (int i = threadIdx.x; i < kDsfEntries; i += kBlk) dsf[i] = d.dsf32[i];
-    __syncthreads();
-  }
   // Unit range of this wave: equal runs of units (the unit cuts already cap
   // each unit's tiles; runs keep a super-cluster's units on one wave).  The
   // wave index is made provably uniform: unit and entry indices then live in
   // scalar registers.  The wave's start record (written with the units for
   // this wave count) gives the run and its first unit without waiting on
   // the unit count; for another wave count the run follows from the count.
+  // (Asked for before the table below, so that the two loads overlap.)
   const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = gridDim.x * (kBlk / 64), w = blockIdx.x * (kBlk / 64) + wib;
   const int4 wrec = d.wrec[w];
   const int4 wu0 = d.wrec_u0[w];
-  const bool rec = d.ctr[CTR_WAVES] == nw;
+  const int rec_waves = d.ctr[CTR_WAVES], n_units = d.ctr[CTR_NUNIT];
+  // FP32 DSF pieces, once per block
+  __shared__ float4 dsf[sizeof(R) == 4 ? kDsfEntries : 1];
+  if (sizeof(R) == 4) {
+    for (int i = threadIdx.x; i < kDsfEntries; i += kBlk) dsf[i] = d.dsf32[i];
+    __syncthreads();
+  }
+  const bool rec = rec_waves == nw;
   int ub, nr;
   if (rec) {
     ub = wrec.x;
     nr = wrec.y;
   } else {
-    const int n_units = d.ctr[CTR_NUNIT];
     ub = (int)((long long)n_units * w / nw);
     nr = (int)((long long)n_units * (w + 1) / nw) - ub;
   }
