@@ -48,9 +48,10 @@ def measured_traffic(name):
 
 def timing_every(K):
     """Stride of the timed tile launches in a K-step timed region: each timed
-    launch carries two HIP events (a few microseconds of stream time), so
-    only a sample of the calls is bracketed (two of a short run)."""
-    return max(1, min(16, K // 2))
+    launch carries two HIP events (about 6 us of stream time), so only a
+    sample of the calls is bracketed (two of a short run, every 64th of a
+    long one: 16 of the default 1,000 calls, ~0.1 us per call)."""
+    return max(1, min(64, K // 2))
 
 
 def run_path(ctx, traj, lams, W, K, torch, graph):
